@@ -1,0 +1,87 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+This module holds no arithmetic of the scheme: it only draws macroscopic
+initial fields (rho, ux, uy, T on an (ny, nx) grid, float64) and domain
+descriptors.  Each side (oracle, HIP library) turns them into populations with
+its own code.  Recipes:
+
+* ``periodic_wave``      -- nonlinear wave on a periodic box: rho = 1 + a cos(kx),
+                            ux = b cos(kx), T uniform (sec. 4 style test, no walls).
+* ``shear_acoustic``     -- ux = 0.01 sin(2 pi y / L), rho = 1 + 1e-3 cos(2 pi x / L),
+                            T uniform (transverse shear wave + sound wave, sec. 6).
+* ``thermal_mode``       -- T = T0 + dT cos(kx), rho = 1 - (T - T0)/28, at rest: the
+                            non-acoustic diffusive state of sec. 4 (eigenvector
+                            (1, 0, -28) of the first-order system, sec. 6).
+* ``cavity_fields``      -- heated cavity at rest, T = T0 + 1e-3 dT U[-1, 1) noise with
+                            rho = 1 - (T - T0)/28 (numpy default_rng(seed)), sec. 10.
+* ``cavity_batch``       -- square cavities, side ~ U{64..512}, Ra log-uniform in
+                            [1e3, 1e6], Pr ~ U[0.5, 7], one draw order per cavity.
+* ``channel_batch``      -- channels periodic along y: length ~ U{256..2048}, width ~
+                            U{32..256}; even index Couette (west wall velocity ~
+                            U[0.01, 0.05]), odd index Poiseuille (force ~ U[1e-6, 1e-5]);
+                            walls T0 +- dT with dT = 0.01 (secs. 7, 8).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _grid(nx: int, ny: int):
+    x = np.broadcast_to(np.arange(nx, dtype=np.float64)[None, :], (ny, nx))
+    y = np.broadcast_to(np.arange(ny, dtype=np.float64)[:, None], (ny, nx))
+    return x, y
+
+
+def periodic_wave(n: int = 32, T0: float = -2.0, a_rho: float = 0.05, a_u: float = 0.02):
+    x, _ = _grid(n, n)
+    c = np.cos(2.0 * np.pi * x / n)
+    return (1.0 + a_rho * c, a_u * c, np.zeros((n, n)), np.full((n, n), T0))
+
+
+def shear_acoustic(nx: int, ny: int | None = None, T0: float = -2.0, a_u: float = 0.01, a_rho: float = 1e-3):
+    ny = nx if ny is None else ny
+    x, y = _grid(nx, ny)
+    return (1.0 + a_rho * np.cos(2.0 * np.pi * x / nx), a_u * np.sin(2.0 * np.pi * y / ny),
+            np.zeros((ny, nx)), np.full((ny, nx), T0))
+
+
+def thermal_mode(nx: int, ny: int, T0: float = -2.0, dT: float = 1e-4, K: int = 1):
+    x, _ = _grid(nx, ny)
+    dE = dT * np.cos(2.0 * np.pi * K * x / nx)
+    return (1.0 - dE / 28.0, np.zeros((ny, nx)), np.zeros((ny, nx)), T0 + dE)
+
+
+def cavity_fields(n: int, T0: float = -2.0, dT: float = 0.01, seed: int = 0, ny: int | None = None):
+    ny = n if ny is None else ny
+    rng = np.random.default_rng(seed)
+    dE = 1e-3 * dT * rng.uniform(-1.0, 1.0, size=(ny, n))
+    return (1.0 - dE / 28.0, np.zeros((ny, n)), np.zeros((ny, n)), T0 + dE)
+
+
+def cavity_batch(count: int = 64, seed: int = 4, side_lo: int = 64, side_hi: int = 512):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        side = int(rng.integers(side_lo, side_hi + 1))
+        Ra = float(10.0 ** rng.uniform(3.0, 6.0))
+        Pr = float(rng.uniform(0.5, 7.0))
+        out.append(dict(nx=side, ny=side, Ra=Ra, Pr=Pr))
+    return out
+
+
+def channel_batch(count: int = 128, seed: int = 5, len_lo: int = 256, len_hi: int = 2048,
+                  w_lo: int = 32, w_hi: int = 256, dT: float = 0.01):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        L = int(rng.integers(len_lo, len_hi + 1))
+        W = int(rng.integers(w_lo, w_hi + 1))
+        if i % 2 == 0:
+            out.append(dict(nx=W, ny=L, kind="couette", U=float(rng.uniform(0.01, 0.05)), F=0.0, dT=dT))
+        else:
+            out.append(dict(nx=W, ny=L, kind="poiseuille", U=0.0, F=float(rng.uniform(1e-6, 1e-5)), dT=dT))
+    return out
+
+
+def rest_fields(nx: int, ny: int, T0: float = -2.0):
+    return (np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)), np.full((ny, nx), T0))
