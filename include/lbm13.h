@@ -1,0 +1,214 @@
+/*
+ * lbm13.h -- C ABI of the MI355X (gfx950) D2Q13 "energy-conserving" lattice
+ * Boltzmann step of Lallemand & Dubois, "Comparison of Simulations of Convective
+ * Flows" (Commun. Comput. Phys. 2015).
+ *
+ * One time step (sec. 2, sec. 7): at every node the 13 populations are mapped
+ * to the 13 orthogonal moments of eq (d2q13-polynomes); rho, E, jx, jy are
+ * conserved; the nine other moments relax toward the equilibria of eq
+ * (d2q13-moments-equil) with the rates of eqs (d2q13-henon), (d2q13-diffusion),
+ * (d2q13-sigma-qx); the body force (secs. 5, 8) is added to j; the inverse
+ * transform gives the post-collision populations, which move along the 13
+ * velocities (eq d2q13-vitesses, reach 1 and 2).  Links that leave the domain
+ * through a wall come back by bounce-back (links with a tangential component,
+ * and every link at an adiabatic wall) or anti-bounce-back (links normal to a
+ * temperature wall), eq (d2q13-cl-abb).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns an int status (LBM13_OK or a negative code); no
+ *    exception, abort or exit crosses the ABI.  lbm13_last_error() gives a
+ *    message for the last failing call on a context.
+ *  - Device memory is owned by the caller: lbm13_create() adopts a device
+ *    workspace of lbm13_workspace_bytes() bytes and never frees it.  Field
+ *    arguments marked "device" are device pointers, row-major [y][x] with x
+ *    fastest, nx*ny doubles each, unless stated otherwise.
+ *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as void*;
+ *    NULL = the null stream) and is asynchronous unless a call says it
+ *    synchronises.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Grid: node (x, y), 0 <= x < nx, 0 <= y < ny, nx, ny >= 2.  A non-periodic
+ *    side is a straight wall half a spacing outside the first/last node.
+ *  - State: the library keeps the post-collision populations f*(t) of the
+ *    current step, stored as deviations from the rest populations
+ *    f^eq(rho = 1, j = 0, E = E0) in FP64 or FP32 (precision chosen at create).
+ */
+#ifndef LBM13_H
+#define LBM13_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LBM13_OK 0
+#define LBM13_EINVAL (-1)           /* bad argument, size or pointer */
+#define LBM13_ENOMEM (-2)           /* workspace smaller than lbm13_workspace_bytes() */
+#define LBM13_EDEVICE (-3)          /* a HIP runtime call or kernel launch failed */
+#define LBM13_EUNSTABLE_PARAMS (-4) /* a relaxation rate (given or derived) outside (0, 2), or degenerate constants */
+#define LBM13_ENONFINITE (-5)       /* diagnostics found a non-finite population or rho <= 0 */
+#define LBM13_ESTATE (-6)           /* call out of order (e.g. step before set_params / init) */
+
+/* storage and arithmetic precision of the populations */
+#define LBM13_FP64 0      /* FP64 storage and collision */
+#define LBM13_FP32_DEV 1  /* FP32 deviations from rest, FP32 collision, FP64 reductions */
+
+/* side kinds; sides are indexed 0 = West (x = -1/2), 1 = East (x = nx - 1/2),
+ * 2 = South (y = -1/2), 3 = North (y = ny - 1/2).  Opposite sides are both
+ * periodic or both walls. */
+#define LBM13_PERIODIC 0
+#define LBM13_WALL_ADIABATIC 1   /* bounce-back on every link: no mass or energy flux (sec. 9, Table 1 cavity) */
+#define LBM13_WALL_DIRICHLET_T 2 /* bounce-back on tangential links, anti-bounce-back on normal links (sec. 7) */
+
+/* One side of the domain.  u_tangential: wall velocity along the wall (along y
+ * for West/East, along x for South/North).  T_wall: imposed temperature
+ * T = E - (13/2)|u|^2 (sec. 7), used by LBM13_WALL_DIRICHLET_T sides. */
+typedef struct {
+    int kind;
+    double u_tangential;
+    double T_wall;
+} lbm13_side;
+
+/* Free parameters of the scheme, as listed after eq (d2q13-sigma-qx): the
+ * Prandtl number, E0 (energy of the rest state at rho = 1), c1, k2, c_epsE,
+ * c_varpi_rho, c_varpi_E and the relaxation rates s_XX (also used for XY),
+ * s_rx (also ry), s_eps, s_varpi, s_XXe.  Forces: F = F0 + g (rho - rho0) is
+ * added to j after relaxation (F0: sec. 8 pressure gradient; g: sec. 5
+ * buoyancy).  collide = 0 skips the collision (streaming and walls only). */
+typedef struct {
+    double s_XX, s_rx, s_eps, s_varpi, s_XXe;
+    double Pr, E0, c1, k2, c_epsE, c_varpi_rho, c_varpi_E;
+    double F0[2];
+    double g[2];
+    double rho0;
+    int collide;
+} lbm13_params;
+
+/* Coefficients derived from lbm13_params by the constraints of eqs
+ * (d2q13-diffusion), (d2q13-sigma-qx), and transport coefficients of the
+ * scheme: nu (shear viscosity), kappa = nu/Pr (thermal diffusivity), cs2
+ * (squared sound speed, from eq d2q13-equiv-edp-ordre-1), B (equilibrium
+ * E-flux per unit momentum), kappa_E = kappa (28 + B)/28 (E-conductivity). */
+typedef struct {
+    double A, Y, h1, k1, h2, c2, c_eps_rho;
+    double sigma_XX, sigma_q, s_q;
+    double nu, kappa, cs2, B, kappa_E;
+} lbm13_derived;
+
+typedef struct lbm13_ctx lbm13_ctx;
+
+/* Host-only: derive the constrained coefficients (eqs d2q13-henon,
+ * d2q13-diffusion, d2q13-sigma-qx).  Returns LBM13_EUNSTABLE_PARAMS when a rate
+ * leaves (0, 2) or Pr <= 0; `out` is filled in either case.  No device access. */
+int lbm13_derive(const lbm13_params *p, lbm13_derived *out);
+
+/* Bytes of device workspace a single domain nx x ny in `precision` needs
+ * (both population buffers, parameter block, tile table, reduction partials).
+ * Returns 0 for invalid sizes.  Host-only. */
+size_t lbm13_workspace_bytes(int nx, int ny, int precision);
+
+/* Create a context on the current HIP device.  `workspace` is a device
+ * allocation of at least lbm13_workspace_bytes(nx, ny, precision) bytes, 256-
+ * byte aligned, owned by the caller and kept alive until lbm13_destroy().
+ * `stream` is the hipStream_t every call enqueues on.  *out receives the
+ * context (NULL on failure).  Errors: EINVAL (sizes, NULL), ENOMEM (too small). */
+int lbm13_create(int nx, int ny, int precision, void *workspace, size_t workspace_bytes, void *stream,
+                 lbm13_ctx **out);
+
+/* Set the scheme's parameters and the four sides (W, E, S, N).  Derives the
+ * constrained coefficients on the host in FP64 and uploads them (async copy
+ * of a host staging block that the context owns).  `derived` may be NULL.
+ * Errors: EINVAL (inconsistent periodicity), EUNSTABLE_PARAMS. */
+int lbm13_set_params(lbm13_ctx *ctx, const lbm13_params *p, const lbm13_side sides[4], lbm13_derived *derived);
+
+/* Initial state from macroscopic fields (device pointers, nx*ny doubles):
+ * populations f(0) = f^eq(rho, j = rho u, E = T + (13/2)|u|^2) (sec. 7 relation
+ * between T and E), then one collision, so the kept state is f*(0).  Resets the
+ * step counter.  Requires set_params. */
+int lbm13_init_moments(lbm13_ctx *ctx, const double *rho, const double *ux, const double *uy, const double *T);
+
+/* Enqueue n >= 0 time steps (stream, walls, collide) on the stream. Async. */
+int lbm13_step(lbm13_ctx *ctx, long long n);
+
+/* Macroscopic fields of the current state f(t) (device pointers, nx*ny doubles
+ * each; any of them may be NULL): rho = sum f, u = (j + F/2)/rho with
+ * F = F0 + g(rho - rho0), T = E - (13/2)|u|^2 (sec. 7).  Async. */
+int lbm13_moments(lbm13_ctx *ctx, double *rho, double *ux, double *uy, double *T);
+
+/* FP64 diagnostics of the current state, written to the host array out[16]
+ * (synchronises the stream):
+ *  [0] sum rho  [1] sum jx  [2] sum jy  [3] sum E      (state f(t))
+ *  [4] heat flux: sum over interior faces x+1/2 (1 <= x <= nx-3; every face if
+ *      x is periodic) and rows of the face-crossing flux of (M_E - B) carried
+ *      by f*(t)
+ *  [5] mean Nusselt number, Table 1: [4]/(faces*ny) * nx / (kappa_E (T_W - T_E))
+ *      (0 when T_W == T_E)
+ *  [6] max |u|  [7] max |u(x) + u(xbar)| with xbar the node reflected through
+ *      the domain centre (Fig. 14)  [8] [7]/[6]
+ *  [9] count of non-finite stored values  [10] min rho  [11..15] reserved (0).
+ * Returns LBM13_ENONFINITE (with out filled) when [9] > 0 or [10] <= 0. */
+int lbm13_diagnostics(lbm13_ctx *ctx, double out[16]);
+
+/* Copy the kept post-collision populations f*(t) as absolute FP64 values into
+ * the device array dst[13][ny][nx] (dense), or load them from src (same
+ * layout; the step counter is kept).  Async. */
+int lbm13_get_state(lbm13_ctx *ctx, double *dst);
+int lbm13_set_state(lbm13_ctx *ctx, const double *src);
+
+/* Number of steps taken since the last init/set_state... (init resets it). */
+long long lbm13_steps_done(const lbm13_ctx *ctx);
+
+/* Tile shape of the step kernel: tile_x in {32, 64} nodes along x, tile_y in
+ * {4, 8, 16} rows (tile_x * tile_y >= 256).  Rebuilds the tile table.  EINVAL
+ * for unsupported shapes. */
+int lbm13_set_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
+
+/* Time every supported tile shape for `steps` steps on the current state
+ * (state is advanced, so save it first if needed) and keep the fastest.
+ * Writes the chosen shape to tile_x/tile_y when not NULL.  Synchronises. */
+int lbm13_autotune(lbm13_ctx *ctx, int steps, int *tile_x, int *tile_y);
+
+/* Capture k steps (k even, 2..4096) into a HIP graph that lbm13_step() then
+ * replays for every full block of k steps; k = 0 switches graphs off. */
+int lbm13_use_graph(lbm13_ctx *ctx, int k);
+
+/* Destroy the context (frees host objects and graphs; never the workspace). */
+int lbm13_destroy(lbm13_ctx *ctx);
+
+/* Message of the last failing call on ctx ("" if none; a static message when
+ * ctx is NULL). */
+const char *lbm13_last_error(const lbm13_ctx *ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Batched form: `count` independent domains of uneven sizes, each with its own
+ * parameters and sides, advanced by one launch per step over a single tile
+ * table (optionally replayed as one HIP graph of k steps).  Same conventions
+ * and semantics as the single-domain calls, with a domain index i. */
+typedef struct lbm13_batch lbm13_batch;
+
+size_t lbm13_batch_workspace_bytes(int count, const int *nx, const int *ny, int precision);
+int lbm13_batch_create(int count, const int *nx, const int *ny, int precision, void *workspace,
+                       size_t workspace_bytes, void *stream, lbm13_batch **out);
+int lbm13_batch_set_params(lbm13_batch *b, int i, const lbm13_params *p, const lbm13_side sides[4],
+                           lbm13_derived *derived);
+int lbm13_batch_init_moments(lbm13_batch *b, int i, const double *rho, const double *ux, const double *uy,
+                             const double *T);
+int lbm13_batch_step(lbm13_batch *b, long long n);
+int lbm13_batch_moments(lbm13_batch *b, int i, double *rho, double *ux, double *uy, double *T);
+/* out[16*count]: the 16 diagnostics of lbm13_diagnostics() per domain; syncs. */
+int lbm13_batch_diagnostics(lbm13_batch *b, double *out);
+int lbm13_batch_get_state(lbm13_batch *b, int i, double *dst);
+int lbm13_batch_set_state(lbm13_batch *b, int i, const double *src);
+int lbm13_batch_set_tile(lbm13_batch *b, int tile_x, int tile_y);
+int lbm13_batch_autotune(lbm13_batch *b, int steps, int *tile_x, int *tile_y);
+int lbm13_batch_use_graph(lbm13_batch *b, int k);
+long long lbm13_batch_nodes(const lbm13_batch *b);
+int lbm13_batch_destroy(lbm13_batch *b);
+const char *lbm13_batch_last_error(const lbm13_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM13_H */

@@ -1,0 +1,719 @@
+// lbm13_capi.cpp -- C ABI of the D2Q13 step (declared in include/lbm13.h).
+//
+// Host side: derivation of the constrained coefficients (sec. 2, eqs
+// d2q13-henon, d2q13-diffusion, d2q13-sigma-qx), the workspace layout, the
+// tile tables, HIP graph capture and the tile autotuner.  Every step of the
+// method runs in the kernels of lbm13_kernels.hip; nothing here touches
+// populations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm13.h"
+#include "lbm13_device.h"
+
+#ifndef LBM13_PLANE_PAD
+#define LBM13_PLANE_PAD 256  // elements added to each velocity plane (breaks power-of-two plane strides)
+#endif
+
+namespace lbm13 {
+template <typename R>
+hipError_t launch_step(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, hipStream_t);
+template <typename R>
+hipError_t launch_diag(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, double*, hipStream_t);
+template <typename R>
+hipError_t launch_init(int, int, R*, const Dom<R>*, int, const double*, const double*, const double*, const double*,
+                       const double*, hipStream_t);
+template <typename R>
+hipError_t launch_moments(int, int, const R*, const Dom<R>*, int, double*, double*, double*, double*, hipStream_t);
+template <typename R>
+hipError_t launch_get_state(int, int, const R*, const Dom<R>*, int, double*, hipStream_t);
+template <typename R>
+hipError_t launch_set_state(int, int, R*, const Dom<R>*, int, const double*, hipStream_t);
+}  // namespace lbm13
+
+using lbm13::Dom;
+using lbm13::Tile;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kCoef = 16;  // doubles of init coefficients per domain
+const int kShapes[][2] = {{64, 4}, {64, 8}, {64, 16}, {32, 8}, {32, 16}};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool valid_shape(int tx, int ty) {
+    for (auto& s : kShapes)
+        if (s[0] == tx && s[1] == ty) return true;
+    return false;
+}
+
+struct Layout {
+    size_t doms, coef, tiles_all, tiles_run, part, diag, bufA, bufB, total;
+    size_t buf_bytes;
+    int tmax;
+    std::vector<long long> off;  // per-domain element offset
+    std::vector<int> pitch, plane;
+};
+
+// Deterministic workspace layout for `count` domains.
+bool make_layout(int count, const int* nx, const int* ny, int precision, Layout& L) {
+    if (count <= 0 || !nx || !ny || (precision != LBM13_FP64 && precision != LBM13_FP32_DEV)) return false;
+    const size_t es = precision == LBM13_FP64 ? 8 : 4;
+    const size_t dom_size = precision == LBM13_FP64 ? sizeof(Dom<double>) : sizeof(Dom<float>);
+    L.off.resize(count);
+    L.pitch.resize(count);
+    L.plane.resize(count);
+    long long tmax = 0;
+    size_t elems = 0;
+    for (int d = 0; d < count; ++d) {
+        if (nx[d] < 2 || ny[d] < 2 || nx[d] > (1 << 16) || ny[d] > (1 << 16)) return false;
+        const int pitch = (int)align_up((size_t)nx[d], 64);
+        const size_t plane = align_up((size_t)pitch * ny[d], 64) + LBM13_PLANE_PAD;
+        if (plane * 13 >= (size_t)INT32_MAX) return false;
+        L.pitch[d] = pitch;
+        L.plane[d] = (int)plane;
+        L.off[d] = (long long)elems;
+        elems += align_up(13 * plane, kAlign / es);
+        long long t = 0;
+        for (auto& s : kShapes)
+            t = std::max(t, (long long)((nx[d] + s[0] - 1) / s[0]) * ((ny[d] + s[1] - 1) / s[1]));
+        tmax += t;
+    }
+    if (tmax >= INT32_MAX / 2) return false;
+    L.tmax = (int)tmax;
+    size_t p = 0;
+    L.doms = p;      p = align_up(p + dom_size * count, kAlign);
+    L.coef = p;      p = align_up(p + sizeof(double) * kCoef * count, kAlign);
+    L.tiles_all = p; p = align_up(p + sizeof(Tile) * tmax, kAlign);
+    L.tiles_run = p; p = align_up(p + sizeof(Tile) * tmax, kAlign);
+    L.part = p;      p = align_up(p + sizeof(double) * lbm13::kDiagPartials * tmax, kAlign);
+    L.diag = p;      p = align_up(p + sizeof(double) * lbm13::kDiagOut * count, kAlign);
+    L.buf_bytes = elems * es;
+    L.bufA = p;      p = align_up(p + L.buf_bytes, kAlign);
+    L.bufB = p;      p = align_up(p + L.buf_bytes, kAlign);
+    L.total = p;
+    return true;
+}
+
+// Constraints of sec. 2: eqs (d2q13-henon), (d2q13-diffusion), (d2q13-sigma-qx).
+// Transport coefficients: cs2 from the first-order system (d2q13-equiv-edp-ordre-1),
+// nu = sigma_XX (13 c1 + 95 + 2 E0)/104 from the second-order expansion of the XY
+// moment, kappa = nu / Pr, B = (39 + 13 c1 + 2 E0)/2 the equilibrium E flux per
+// unit momentum, kappa_E = kappa (28 + B)/28.
+int derive(const lbm13_params* p, lbm13_derived* d) {
+    const double c1 = p->c1, E0 = p->E0, k2 = p->k2, ceE = p->c_epsE;
+    const double A = 13.0 * c1 + 95.0 + 2.0 * E0;
+    const double Y = 114404.0 + 51051.0 * c1 - 11492.0 * ceE + 7854.0 * E0;
+    d->A = A;
+    d->Y = Y;
+    d->sigma_XX = 1.0 / p->s_XX - 0.5;
+    d->h1 = 17.0 / 26.0 - 0.5 * c1 - E0 / 13.0;
+    d->k1 = 2.0 / 13.0;
+    d->h2 = -(19.5 + 6.5 * c1 + E0) * k2 - (7.0 / 624.0) * A * (874481.0 + 459459.0 * c1 - 103428.0 * ceE + 70686.0 * E0) / Y;
+    d->sigma_q = -654.5 * d->sigma_XX * A / Y;
+    d->s_q = 1.0 / (d->sigma_q + 0.5);
+    d->c_eps_rho = 140.0 + 28.0 * ceE + A * Y / (22984.0 * p->Pr);
+    d->c2 = -65.0 / 24.0 - 2.625 * (c1 + d->h1 + d->k1 * E0) - k2 * E0 - d->h2;
+    d->nu = d->sigma_XX * A / 104.0;
+    d->kappa = d->nu / p->Pr;
+    d->cs2 = A / 52.0;
+    d->B = 0.5 * (39.0 + 13.0 * c1 + 2.0 * E0);
+    d->kappa_E = d->kappa * (28.0 + d->B) / 28.0;
+    const double rates[6] = {p->s_XX, p->s_rx, p->s_eps, p->s_varpi, p->s_XXe, d->s_q};
+    for (double r : rates)
+        if (!(r > 0.0 && r < 2.0)) return LBM13_EUNSTABLE_PARAMS;
+    if (!(p->Pr > 0.0) || !(Y != 0.0) || !std::isfinite(d->c_eps_rho) || !std::isfinite(d->h2))
+        return LBM13_EUNSTABLE_PARAMS;
+    return LBM13_OK;
+}
+
+// Rest populations f^eq(1, 0, E0) by |v|^2 class (0, 1, 2, 4): the inverse of
+// the orthogonal basis applied to (rho, E, eps, varpi) = (1, E0, eps_eq, varpi_eq).
+void rest_populations(const lbm13_params* p, const lbm13_derived* d, double out[4]) {
+    const double eps = d->c_eps_rho + p->c_epsE * p->E0;
+    const double vp = p->c_varpi_rho + p->c_varpi_E * p->E0;
+    const double ME[4] = {-28, -15, -2, 24}, Me[4] = {140, -2, -67, 34}, Mv[4] = {-12, 8, -6, 1};
+    for (int c = 0; c < 4; ++c)
+        out[c] = 1.0 / 13.0 + ME[c] * p->E0 / 4004.0 + Me[c] * eps / 42196.0 + Mv[c] * vp / 548.0;
+}
+
+}  // namespace
+
+struct lbm13_batch {
+    int count = 0, precision = 0;
+    std::vector<int> nx, ny;
+    Layout L;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    std::vector<unsigned char> dom_host;  // staging of the Dom array
+    std::vector<double> coef_host;
+    std::vector<int> sides_kind;          // 4 per domain
+    std::vector<char> has_params, has_state;
+    std::vector<Tile> all, run;
+    int nbulk = 0, nedge = 0;
+    int tile_x = 64, tile_y = 8;
+    int cur = 0;                          // buffer holding the current state
+    long long steps = 0;
+    int graph_k = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+struct lbm13_ctx {
+    lbm13_batch* b = nullptr;
+};
+
+namespace {
+
+int fail(lbm13_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+int hip_fail(lbm13_batch* b, hipError_t e, const char* where) {
+    return fail(b, LBM13_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t dom_size(const lbm13_batch* b) {
+    return b->precision == LBM13_FP64 ? sizeof(Dom<double>) : sizeof(Dom<float>);
+}
+
+template <typename R>
+Dom<R>* dom_host(lbm13_batch* b, int d) {
+    return reinterpret_cast<Dom<R>*>(b->dom_host.data()) + d;
+}
+
+template <typename R>
+R* buf(lbm13_batch* b, int which) {
+    return reinterpret_cast<R*>(b->ws + (which ? b->L.bufB : b->L.bufA));
+}
+
+template <typename R>
+const Dom<R>* doms_dev(lbm13_batch* b) {
+    return reinterpret_cast<const Dom<R>*>(b->ws + b->L.doms);
+}
+
+void drop_graphs(lbm13_batch* b) {
+    for (int p = 0; p < 2; ++p) {
+        if (b->gexec[p]) (void)hipGraphExecDestroy(b->gexec[p]);
+        if (b->graph[p]) (void)hipGraphDestroy(b->graph[p]);
+        b->gexec[p] = nullptr;
+        b->graph[p] = nullptr;
+    }
+}
+
+bool near_wall_tile(const lbm13_batch* b, int d, int x0, int y0) {
+    const int* k = &b->sides_kind[4 * d];
+    const int x1 = std::min(x0 + b->tile_x, b->nx[d]) - 1, y1 = std::min(y0 + b->tile_y, b->ny[d]) - 1;
+    if (k[0] != LBM13_PERIODIC && (x0 < 2 || x1 >= b->nx[d] - 2)) return true;
+    if (k[2] != LBM13_PERIODIC && (y0 < 2 || y1 >= b->ny[d] - 2)) return true;
+    return false;
+}
+
+template <typename R>
+void set_tile_ranges(lbm13_batch* b) {
+    for (int d = 0; d < b->count; ++d) {
+        dom_host<R>(b, d)->tile0 = 0;
+        dom_host<R>(b, d)->ntiles = 0;
+    }
+    int t = 0;
+    for (int d = 0; d < b->count; ++d) {
+        dom_host<R>(b, d)->tile0 = t;
+        const int n = ((b->nx[d] + b->tile_x - 1) / b->tile_x) * ((b->ny[d] + b->tile_y - 1) / b->tile_y);
+        dom_host<R>(b, d)->ntiles = n;
+        t += n;
+    }
+}
+
+// Rebuild the tile tables for the current tile shape and sides; uploads the
+// tables and the Dom array and synchronises (not a hot path).
+int rebuild(lbm13_batch* b) {
+    b->all.clear();
+    std::vector<Tile> bulk, edge;
+    for (int d = 0; d < b->count; ++d)
+        for (int y0 = 0; y0 < b->ny[d]; y0 += b->tile_y)
+            for (int x0 = 0; x0 < b->nx[d]; x0 += b->tile_x) {
+                const bool e = near_wall_tile(b, d, x0, y0);
+                Tile t{d, x0, y0, e ? 1 : 0};
+                b->all.push_back(t);
+                (e ? edge : bulk).push_back(t);
+            }
+    if ((int)b->all.size() > b->L.tmax) return fail(b, LBM13_EINVAL, "tile table overflow");
+    b->run = bulk;
+    b->run.insert(b->run.end(), edge.begin(), edge.end());
+    b->nbulk = (int)bulk.size();
+    b->nedge = (int)edge.size();
+    if (b->precision == LBM13_FP64) set_tile_ranges<double>(b);
+    else set_tile_ranges<float>(b);
+    hipError_t e;
+    e = hipMemcpyAsync(b->ws + b->L.tiles_all, b->all.data(), sizeof(Tile) * b->all.size(), hipMemcpyHostToDevice,
+                       b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "upload tile table");
+    e = hipMemcpyAsync(b->ws + b->L.tiles_run, b->run.data(), sizeof(Tile) * b->run.size(), hipMemcpyHostToDevice,
+                       b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "upload tile table");
+    e = hipMemcpyAsync(b->ws + b->L.doms, b->dom_host.data(), b->dom_host.size(), hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "upload domain table");
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "synchronise");
+    drop_graphs(b);
+    return LBM13_OK;
+}
+
+template <typename R>
+void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* sides, const lbm13_derived* dv) {
+    Dom<R>* D = dom_host<R>(b, d);
+    const int tile0 = D->tile0, ntiles = D->ntiles;
+    std::memset(D, 0, sizeof(Dom<R>));
+    D->tile0 = tile0;
+    D->ntiles = ntiles;
+    D->off = b->L.off[d];
+    D->plane = b->L.plane[d];
+    D->pitch = b->L.pitch[d];
+    D->nx = b->nx[d];
+    D->ny = b->ny[d];
+    D->xper = sides[0].kind == LBM13_PERIODIC;
+    D->yper = sides[2].kind == LBM13_PERIODIC;
+    for (int w = 0; w < 4; ++w) D->kind[w] = sides[w].kind;
+    D->collide = p->collide ? 1 : 0;
+    const double a1 = p->c1 + dv->h1 + dv->k1 * p->E0;
+    const double a2 = dv->c2 + dv->h2 + p->k2 * p->E0;
+    D->s_eps = R(p->s_eps);
+    D->s_vp = R(p->s_varpi);
+    D->s_q = R(dv->s_q);
+    D->s_r = R(p->s_rx);
+    D->s_XX = R(p->s_XX);
+    D->s_XXe = R(p->s_XXe);
+    D->c_er = R(dv->c_eps_rho);
+    D->c_eE = R(p->c_epsE);
+    D->c_vr = R(p->c_varpi_rho);
+    D->c_vE = R(p->c_varpi_E);
+    D->a1 = R(a1);
+    D->h1 = R(dv->h1);
+    D->k1 = R(dv->k1);
+    D->a2 = R(a2);
+    D->h2 = R(dv->h2);
+    D->k2 = R(p->k2);
+    const double F0x = p->F0[0] + p->g[0] * (1.0 - p->rho0), F0y = p->F0[1] + p->g[1] * (1.0 - p->rho0);
+    D->F0x = R(F0x);
+    D->F0y = R(F0y);
+    D->gx = R(p->g[0]);
+    D->gy = R(p->g[1]);
+    D->F0x_d = F0x;
+    D->F0y_d = F0y;
+    D->gx_d = p->g[0];
+    D->gy_d = p->g[1];
+    for (int w = 0; w < 4; ++w) {
+        const double u = sides[w].u_tangential;
+        D->wall_u[w] = R(u);
+        D->wall_dE[w] = R(sides[w].kind == LBM13_WALL_DIRICHLET_T ? sides[w].T_wall + 6.5 * u * u - p->E0 : 0.0);
+    }
+    D->E0 = p->E0;
+    rest_populations(p, dv, D->frest);
+    D->B = dv->B;
+    const double dT = sides[0].T_wall - sides[1].T_wall;
+    D->nu_scale = dT != 0.0 ? (double)b->nx[d] / (dv->kappa_E * dT) : 0.0;
+    double* c = &b->coef_host[(size_t)kCoef * d];
+    const double cc[10] = {dv->c_eps_rho, p->c_epsE, p->c_varpi_rho, p->c_varpi_E, a1, dv->h1, dv->k1,
+                           a2, dv->h2, p->k2};
+    for (int k = 0; k < 10; ++k) c[k] = cc[k];
+}
+
+bool check_index(lbm13_batch* b, int i) { return b && i >= 0 && i < b->count; }
+
+template <typename R>
+int do_step(lbm13_batch* b, int from) {
+    const Tile* run = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_run);
+    hipError_t e = lbm13::launch_step<R>(b->tile_x, b->tile_y, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b),
+                                         run, b->nbulk, run + b->nbulk, b->nedge, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "step launch");
+    return LBM13_OK;
+}
+
+template <typename R>
+int capture_graph(lbm13_batch* b, int parity) {
+    hipError_t e;
+    if (!b->capture_stream) {
+        e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(b, e, "create capture stream");
+    }
+    e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(b, e, "begin capture");
+    const Tile* run = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_run);
+    int from = parity;
+    hipError_t le = hipSuccess;
+    for (int s = 0; s < b->graph_k && le == hipSuccess; ++s) {
+        le = lbm13::launch_step<R>(b->tile_x, b->tile_y, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), run,
+                                   b->nbulk, run + b->nbulk, b->nedge, b->capture_stream);
+        from = 1 - from;
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->capture_stream, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(b, le, "launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(b, e, "end capture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(b, e, "instantiate graph");
+    }
+    b->graph[parity] = g;
+    b->gexec[parity] = x;
+    return LBM13_OK;
+}
+
+template <typename R>
+int step_impl(lbm13_batch* b, long long n) {
+    while (b->graph_k > 0 && n >= b->graph_k) {
+        if (!b->gexec[b->cur]) {
+            int st = capture_graph<R>(b, b->cur);
+            if (st) return st;
+        }
+        hipError_t e = hipGraphLaunch(b->gexec[b->cur], b->stream);
+        if (e != hipSuccess) return hip_fail(b, e, "graph launch");
+        n -= b->graph_k;
+        b->steps += b->graph_k;
+    }
+    for (long long s = 0; s < n; ++s) {
+        int st = do_step<R>(b, b->cur);
+        if (st) return st;
+        b->cur = 1 - b->cur;
+        b->steps += 1;
+    }
+    return LBM13_OK;
+}
+
+int ready(lbm13_batch* b) {
+    if (!b) return LBM13_EINVAL;
+    for (int d = 0; d < b->count; ++d) {
+        if (!b->has_params[d]) return fail(b, LBM13_ESTATE, "domain " + std::to_string(d) + " has no parameters");
+        if (!b->has_state[d]) return fail(b, LBM13_ESTATE, "domain " + std::to_string(d) + " has no initial state");
+    }
+    return LBM13_OK;
+}
+
+template <typename R>
+int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(b, LBM13_EDEVICE, "event create");
+    const int keep_k = b->graph_k;
+    b->graph_k = 0;
+    float best = 1e30f;
+    int bx = b->tile_x, by = b->tile_y;
+    int st = LBM13_OK;
+    for (auto& s : kShapes) {
+        b->tile_x = s[0];
+        b->tile_y = s[1];
+        if ((st = rebuild(b))) break;
+        if ((st = step_impl<R>(b, 2))) break;
+        (void)hipEventRecord(e0, b->stream);
+        if ((st = step_impl<R>(b, steps))) break;
+        (void)hipEventRecord(e1, b->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(b, LBM13_EDEVICE, "event sync");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            bx = s[0];
+            by = s[1];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tile_x = bx;
+    b->tile_y = by;
+    int st2 = rebuild(b);
+    b->graph_k = keep_k;
+    if (st) return st;
+    if (st2) return st2;
+    if (tx) *tx = bx;
+    if (ty) *ty = by;
+    return LBM13_OK;
+}
+
+}  // namespace
+
+// =========================================================================== batch API
+
+extern "C" {
+
+int lbm13_derive(const lbm13_params* p, lbm13_derived* out) {
+    if (!p || !out) return LBM13_EINVAL;
+    return derive(p, out);
+}
+
+size_t lbm13_batch_workspace_bytes(int count, const int* nx, const int* ny, int precision) {
+    Layout L;
+    if (!make_layout(count, nx, ny, precision, L)) return 0;
+    return L.total;
+}
+
+int lbm13_batch_create(int count, const int* nx, const int* ny, int precision, void* workspace,
+                       size_t workspace_bytes, void* stream, lbm13_batch** out) {
+    if (!out) return LBM13_EINVAL;
+    *out = nullptr;
+    Layout L;
+    if (!make_layout(count, nx, ny, precision, L) || !workspace) return LBM13_EINVAL;
+    if (workspace_bytes < L.total) return LBM13_ENOMEM;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return LBM13_EINVAL;
+    lbm13_batch* b = new (std::nothrow) lbm13_batch;
+    if (!b) return LBM13_ENOMEM;
+    b->count = count;
+    b->precision = precision;
+    b->nx.assign(nx, nx + count);
+    b->ny.assign(ny, ny + count);
+    b->L = L;
+    b->ws = static_cast<char*>(workspace);
+    b->stream = static_cast<hipStream_t>(stream);
+    b->dom_host.assign(dom_size(b) * count, 0);
+    b->coef_host.assign((size_t)kCoef * count, 0.0);
+    b->sides_kind.assign(4 * count, LBM13_PERIODIC);
+    b->has_params.assign(count, 0);
+    b->has_state.assign(count, 0);
+    int st = rebuild(b);
+    if (st) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return LBM13_OK;
+}
+
+int lbm13_batch_set_params(lbm13_batch* b, int i, const lbm13_params* p, const lbm13_side sides[4],
+                           lbm13_derived* derived) {
+    if (!check_index(b, i) || !p || !sides) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    for (int w = 0; w < 4; ++w)
+        if (sides[w].kind < LBM13_PERIODIC || sides[w].kind > LBM13_WALL_DIRICHLET_T)
+            return fail(b, LBM13_EINVAL, "unknown side kind");
+    if ((sides[0].kind == LBM13_PERIODIC) != (sides[1].kind == LBM13_PERIODIC) ||
+        (sides[2].kind == LBM13_PERIODIC) != (sides[3].kind == LBM13_PERIODIC))
+        return fail(b, LBM13_EINVAL, "opposite sides must both be periodic or both walls");
+    lbm13_derived dv;
+    int st = derive(p, &dv);
+    if (derived) *derived = dv;
+    if (st) return fail(b, st, "relaxation rate outside (0, 2) or degenerate constants");
+    for (int w = 0; w < 4; ++w) b->sides_kind[4 * i + w] = sides[w].kind;
+    if (b->precision == LBM13_FP64) fill_dom<double>(b, i, p, sides, &dv);
+    else fill_dom<float>(b, i, p, sides, &dv);
+    hipError_t e = hipMemcpyAsync(b->ws + b->L.coef + sizeof(double) * kCoef * i, &b->coef_host[(size_t)kCoef * i],
+                                  sizeof(double) * kCoef, hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "upload coefficients");
+    b->has_params[i] = 1;
+    return rebuild(b);
+}
+
+int lbm13_batch_init_moments(lbm13_batch* b, int i, const double* rho, const double* ux, const double* uy,
+                             const double* T) {
+    if (!check_index(b, i) || !rho || !ux || !uy || !T) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    if (!b->has_params[i]) return fail(b, LBM13_ESTATE, "set_params first");
+    const double* coef = reinterpret_cast<const double*>(b->ws + b->L.coef) + (size_t)kCoef * i;
+    hipError_t e;
+    if (b->precision == LBM13_FP64)
+        e = lbm13::launch_init<double>(b->nx[i], b->ny[i], buf<double>(b, b->cur), doms_dev<double>(b), i, rho, ux, uy,
+                                       T, coef, b->stream);
+    else
+        e = lbm13::launch_init<float>(b->nx[i], b->ny[i], buf<float>(b, b->cur), doms_dev<float>(b), i, rho, ux, uy, T,
+                                      coef, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "init launch");
+    b->has_state[i] = 1;
+    b->steps = 0;
+    return LBM13_OK;
+}
+
+int lbm13_batch_step(lbm13_batch* b, long long n) {
+    if (!b || n < 0) return b ? fail(b, LBM13_EINVAL, "negative step count") : LBM13_EINVAL;
+    int st = ready(b);
+    if (st) return st;
+    return b->precision == LBM13_FP64 ? step_impl<double>(b, n) : step_impl<float>(b, n);
+}
+
+int lbm13_batch_moments(lbm13_batch* b, int i, double* rho, double* ux, double* uy, double* T) {
+    if (!check_index(b, i)) return b ? fail(b, LBM13_EINVAL, "bad domain index") : LBM13_EINVAL;
+    if (!b->has_state[i]) return fail(b, LBM13_ESTATE, "no state");
+    hipError_t e;
+    if (b->precision == LBM13_FP64)
+        e = lbm13::launch_moments<double>(b->nx[i], b->ny[i], buf<double>(b, b->cur), doms_dev<double>(b), i, rho, ux,
+                                          uy, T, b->stream);
+    else
+        e = lbm13::launch_moments<float>(b->nx[i], b->ny[i], buf<float>(b, b->cur), doms_dev<float>(b), i, rho, ux, uy,
+                                         T, b->stream);
+    return e == hipSuccess ? LBM13_OK : hip_fail(b, e, "moments launch");
+}
+
+int lbm13_batch_diagnostics(lbm13_batch* b, double* out) {
+    if (!b || !out) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    int st = ready(b);
+    if (st) return st;
+    const Tile* all = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_all);
+    double* part = reinterpret_cast<double*>(b->ws + b->L.part);
+    double* dout = reinterpret_cast<double*>(b->ws + b->L.diag);
+    hipError_t e;
+    if (b->precision == LBM13_FP64)
+        e = lbm13::launch_diag<double>(b->tile_x, b->tile_y, buf<double>(b, b->cur), doms_dev<double>(b), b->count, all,
+                                       (int)b->all.size(), part, dout, b->stream);
+    else
+        e = lbm13::launch_diag<float>(b->tile_x, b->tile_y, buf<float>(b, b->cur), doms_dev<float>(b), b->count, all,
+                                      (int)b->all.size(), part, dout, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "diagnostics launch");
+    e = hipMemcpyAsync(out, dout, sizeof(double) * lbm13::kDiagOut * b->count, hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "diagnostics copy");
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "diagnostics sync");
+    for (int d = 0; d < b->count; ++d)
+        if (out[lbm13::kDiagOut * d + 9] > 0 || !(out[lbm13::kDiagOut * d + 10] > 0))
+            return fail(b, LBM13_ENONFINITE, "non-finite population or rho <= 0 in domain " + std::to_string(d));
+    return LBM13_OK;
+}
+
+int lbm13_batch_get_state(lbm13_batch* b, int i, double* dst) {
+    if (!check_index(b, i) || !dst) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    if (!b->has_state[i]) return fail(b, LBM13_ESTATE, "no state");
+    if (!b->has_params[i]) return fail(b, LBM13_ESTATE, "no parameters");
+    hipError_t e;
+    if (b->precision == LBM13_FP64)
+        e = lbm13::launch_get_state<double>(b->nx[i], b->ny[i], buf<double>(b, b->cur), doms_dev<double>(b), i, dst,
+                                            b->stream);
+    else
+        e = lbm13::launch_get_state<float>(b->nx[i], b->ny[i], buf<float>(b, b->cur), doms_dev<float>(b), i, dst,
+                                           b->stream);
+    return e == hipSuccess ? LBM13_OK : hip_fail(b, e, "get_state launch");
+}
+
+int lbm13_batch_set_state(lbm13_batch* b, int i, const double* src) {
+    if (!check_index(b, i) || !src) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    if (!b->has_params[i]) return fail(b, LBM13_ESTATE, "set_params first");
+    hipError_t e;
+    if (b->precision == LBM13_FP64)
+        e = lbm13::launch_set_state<double>(b->nx[i], b->ny[i], buf<double>(b, b->cur), doms_dev<double>(b), i, src,
+                                            b->stream);
+    else
+        e = lbm13::launch_set_state<float>(b->nx[i], b->ny[i], buf<float>(b, b->cur), doms_dev<float>(b), i, src,
+                                           b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "set_state launch");
+    b->has_state[i] = 1;
+    return LBM13_OK;
+}
+
+int lbm13_batch_set_tile(lbm13_batch* b, int tile_x, int tile_y) {
+    if (!b) return LBM13_EINVAL;
+    if (!valid_shape(tile_x, tile_y)) return fail(b, LBM13_EINVAL, "unsupported tile shape");
+    b->tile_x = tile_x;
+    b->tile_y = tile_y;
+    return rebuild(b);
+}
+
+int lbm13_batch_autotune(lbm13_batch* b, int steps, int* tile_x, int* tile_y) {
+    if (!b || steps <= 0) return b ? fail(b, LBM13_EINVAL, "steps must be positive") : LBM13_EINVAL;
+    int st = ready(b);
+    if (st) return st;
+    return b->precision == LBM13_FP64 ? autotune_impl<double>(b, steps, tile_x, tile_y)
+                                      : autotune_impl<float>(b, steps, tile_x, tile_y);
+}
+
+int lbm13_batch_use_graph(lbm13_batch* b, int k) {
+    if (!b) return LBM13_EINVAL;
+    if (k != 0 && (k < 2 || k > 4096 || (k & 1))) return fail(b, LBM13_EINVAL, "graph length must be even, 2..4096");
+    drop_graphs(b);
+    b->graph_k = k;
+    return LBM13_OK;
+}
+
+long long lbm13_batch_nodes(const lbm13_batch* b) {
+    if (!b) return 0;
+    long long n = 0;
+    for (int d = 0; d < b->count; ++d) n += (long long)b->nx[d] * b->ny[d];
+    return n;
+}
+
+int lbm13_batch_destroy(lbm13_batch* b) {
+    if (!b) return LBM13_EINVAL;
+    drop_graphs(b);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    delete b;
+    return LBM13_OK;
+}
+
+const char* lbm13_batch_last_error(const lbm13_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+// =========================================================================== single-domain API
+
+size_t lbm13_workspace_bytes(int nx, int ny, int precision) {
+    return lbm13_batch_workspace_bytes(1, &nx, &ny, precision);
+}
+
+int lbm13_create(int nx, int ny, int precision, void* workspace, size_t workspace_bytes, void* stream,
+                 lbm13_ctx** out) {
+    if (!out) return LBM13_EINVAL;
+    *out = nullptr;
+    lbm13_ctx* c = new (std::nothrow) lbm13_ctx;
+    if (!c) return LBM13_ENOMEM;
+    int st = lbm13_batch_create(1, &nx, &ny, precision, workspace, workspace_bytes, stream, &c->b);
+    if (st) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return LBM13_OK;
+}
+
+int lbm13_set_params(lbm13_ctx* c, const lbm13_params* p, const lbm13_side sides[4], lbm13_derived* derived) {
+    return c ? lbm13_batch_set_params(c->b, 0, p, sides, derived) : LBM13_EINVAL;
+}
+
+int lbm13_init_moments(lbm13_ctx* c, const double* rho, const double* ux, const double* uy, const double* T) {
+    return c ? lbm13_batch_init_moments(c->b, 0, rho, ux, uy, T) : LBM13_EINVAL;
+}
+
+int lbm13_step(lbm13_ctx* c, long long n) { return c ? lbm13_batch_step(c->b, n) : LBM13_EINVAL; }
+
+int lbm13_moments(lbm13_ctx* c, double* rho, double* ux, double* uy, double* T) {
+    return c ? lbm13_batch_moments(c->b, 0, rho, ux, uy, T) : LBM13_EINVAL;
+}
+
+int lbm13_diagnostics(lbm13_ctx* c, double out[16]) { return c ? lbm13_batch_diagnostics(c->b, out) : LBM13_EINVAL; }
+
+int lbm13_get_state(lbm13_ctx* c, double* dst) { return c ? lbm13_batch_get_state(c->b, 0, dst) : LBM13_EINVAL; }
+
+int lbm13_set_state(lbm13_ctx* c, const double* src) {
+    return c ? lbm13_batch_set_state(c->b, 0, src) : LBM13_EINVAL;
+}
+
+long long lbm13_steps_done(const lbm13_ctx* c) { return c && c->b ? c->b->steps : 0; }
+
+int lbm13_set_tile(lbm13_ctx* c, int tile_x, int tile_y) {
+    return c ? lbm13_batch_set_tile(c->b, tile_x, tile_y) : LBM13_EINVAL;
+}
+
+int lbm13_autotune(lbm13_ctx* c, int steps, int* tile_x, int* tile_y) {
+    return c ? lbm13_batch_autotune(c->b, steps, tile_x, tile_y) : LBM13_EINVAL;
+}
+
+int lbm13_use_graph(lbm13_ctx* c, int k) { return c ? lbm13_batch_use_graph(c->b, k) : LBM13_EINVAL; }
+
+int lbm13_destroy(lbm13_ctx* c) {
+    if (!c) return LBM13_EINVAL;
+    int st = lbm13_batch_destroy(c->b);
+    delete c;
+    return st;
+}
+
+const char* lbm13_last_error(const lbm13_ctx* c) { return c ? lbm13_batch_last_error(c->b) : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// lbm13_device.h -- device-side data structures of the D2Q13 step (gfx950).
+//
+// Populations are stored as deviations g_i = f*_i - f_i^rest from the rest
+// populations f^rest = f^eq(rho = 1, j = 0, E = E0), one plane per velocity
+// (structure of arrays): element (i, y, x) of a domain sits at
+//   base + off + i * plane + y * pitch + x.
+// Keeping deviations lets the FP32 form collide without cancelling O(1) terms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lbm13 {
+
+enum SideKind { kPeriodic = 0, kAdiabatic = 1, kDirichletT = 2 };
+
+// Per-domain descriptor: geometry, collision constants in the working precision
+// R (deviation form), FP64 constants for read-back and diagnostics.
+template <typename R>
+struct alignas(16) Dom {
+    long long off;    // element offset of plane 0 of this domain in each population buffer
+    int plane;        // elements between two velocity planes
+    int pitch;        // elements between two rows
+    int nx, ny;
+    int xper, yper;   // 1 when the axis is periodic
+    int kind[4];      // W, E, S, N
+    int tile0, ntiles;  // range of this domain in the domain-ordered tile table
+    int collide;
+    int pad0;
+    // relaxation rates of eps, varpi, q (x and y), r (x and y), XX (and XY), XXe
+    R s_eps, s_vp, s_q, s_r, s_XX, s_XXe;
+    // equilibria about rest: eps' = c_er rho' + c_eE E', varpi' = c_vr rho' + c_vE E',
+    // q = j (a1 + h1 rho' + k1 E'), r = j (a2 + h2 rho' + k2 E'),  (rho', E' deviations)
+    R c_er, c_eE, c_vr, c_vE;
+    R a1, h1, k1, a2, h2, k2;
+    // body force F = F0 + g rho' (F0 already holds F0 + g (1 - rho0))
+    R F0x, F0y, gx, gy;
+    // walls: tangential velocity, E_W - E0 for temperature walls
+    R wall_u[4];
+    R wall_dE[4];
+    // FP64 constants
+    double E0;
+    double frest[4];  // rest populations of the |v|^2 = 0, 1, 2, 4 classes
+    double F0x_d, F0y_d, gx_d, gy_d;
+    double B;         // equilibrium E flux per unit momentum
+    double nu_scale;  // nx / (kappa_E (T_W - T_E)), 0 when T_W == T_E
+};
+
+// One tile of the tile tables: domain index, origin, flags (bit 0: tile holds
+// nodes within two nodes of a wall).
+struct alignas(16) Tile {
+    int dom, x0, y0, flags;
+};
+
+constexpr int kDiagPartials = 10;  // per-tile partial reductions
+constexpr int kDiagOut = 16;       // values per domain
+
+}  // namespace lbm13

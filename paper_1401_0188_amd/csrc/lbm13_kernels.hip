@@ -1,0 +1,643 @@
+// lbm13_kernels.hip -- HIP kernels of the D2Q13 energy-conserving lattice
+// Boltzmann step for CDNA4 (gfx950).
+//
+// Scheme: Lallemand & Dubois, "Comparison of Simulations of Convective Flows",
+// sec. 2 (velocities, moments, equilibria, constraints), secs. 5 and 8 (body
+// forces), sec. 7 (mixed bounce-back / anti-bounce-back walls, temperature).
+//
+// The step is a pull: each node gathers the 13 post-collision populations of
+// the previous step from x - v_i (reach 1 and 2), substitutes wall links,
+// collides in registers and writes its 13 new post-collision values with
+// coalesced non-temporal stores.  One wavefront covers 64 (or 2 x 32)
+// consecutive nodes of a row, so every population plane is read and written
+// as contiguous 256/512-byte segments; the +-1/+-2 shifted reads of
+// neighbouring wavefronts share cache lines in L2.
+#include <hip/hip_runtime.h>
+
+#include "lbm13_device.h"
+
+namespace lbm13 {
+
+// Velocity set (eq d2q13-vitesses) and the moment matrix of eq (d2q13-polynomes)
+// with the q polynomial read as x(x^2 + y^2 - 3), rows rho, E, eps, varpi, jx,
+// jy, qx, qy, rx, ry, XX, XY, XXe.  Used by the wall path and the diagnostics;
+// the bulk collision below uses the same matrix in pair-symmetric form.
+__constant__ int c_vx[13] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0};
+__constant__ int c_vy[13] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2};
+__constant__ int c_opp[13] = {0, 3, 4, 1, 2, 7, 8, 5, 6, 11, 12, 9, 10};
+__constant__ int c_cls[13] = {0, 1, 1, 1, 1, 2, 2, 2, 2, 3, 3, 3, 3};  // |v|^2 class
+__constant__ float c_M[13][13] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-28, -15, -15, -15, -15, -2, -2, -2, -2, 24, 24, 24, 24},
+    {140, -2, -2, -2, -2, -67, -67, -67, -67, 34, 34, 34, 34},
+    {-12, 8, 8, 8, 8, -6, -6, -6, -6, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2},
+    {0, -2, 0, 2, 0, -1, 1, 1, -1, 2, 0, -2, 0},
+    {0, 0, -2, 0, 2, -1, -1, 1, 1, 0, 2, 0, -2},
+    {0, 4, 0, -4, 0, -3, 3, 3, -3, 1, 0, -1, 0},
+    {0, 0, 4, 0, -4, -3, -3, 3, 3, 0, 1, 0, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0, 4, -4, 4, -4},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, -4, 4, -4, 4, 0, 0, 0, 0, 1, -1, 1, -1}};
+__constant__ float c_D[13] = {13, 4004, 42196, 548, 14, 14, 20, 20, 70, 70, 68, 4, 68};
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// ---------------------------------------------------------------------------
+// Collision of one node, in place on the deviations g (sec. 2):
+//   m = M g; Delta_k = s_k (m_k - m_k^eq) on the nine non-conserved moments;
+//   j* = j + F; g* = g - M^T D^-1 Delta.
+// Pairs (i, opposite of i) give sums s (even moments) and differences d (odd
+// moments); the inverse splits the same way.
+template <typename R>
+__device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
+    const R s13 = g[1] + g[3], d13 = g[1] - g[3];
+    const R s24 = g[2] + g[4], d24 = g[2] - g[4];
+    const R s57 = g[5] + g[7], d57 = g[5] - g[7];
+    const R s68 = g[6] + g[8], d68 = g[6] - g[8];
+    const R s9 = g[9] + g[11], d9 = g[9] - g[11];
+    const R s10 = g[10] + g[12], d10 = g[10] - g[12];
+    const R S1 = s13 + s24, S2 = s57 + s68, S3 = s9 + s10;
+    const R rho = g[0] + S1 + S2 + S3;  // rho - 1
+    const R E = R(-28) * g[0] - R(15) * S1 - R(2) * S2 + R(24) * S3;  // E - E0
+    const R eps = R(140) * g[0] - R(2) * S1 - R(67) * S2 + R(34) * S3;
+    const R vp = R(-12) * g[0] + R(8) * S1 - R(6) * S2 + S3;
+    const R A1 = s13 - s24, A3 = s9 - s10;
+    const R XX = A1 + R(4) * A3;
+    const R XY = s57 - s68;
+    const R XXe = R(-4) * A1 + A3;
+    const R jx = d13 + d57 - d68 + R(2) * d9;
+    const R jy = d24 + d57 + d68 + R(2) * d10;
+    const R qx = R(-2) * d13 - d57 + d68 + R(2) * d9;
+    const R qy = R(-2) * d24 - d57 - d68 + R(2) * d10;
+    const R rx = R(4) * d13 - R(3) * d57 + R(3) * d68 + d9;
+    const R ry = R(4) * d24 - R(3) * d57 - R(3) * d68 + d10;
+
+    const R inv_rho = R(1) / (R(1) + rho);
+    const R fq = D.a1 + D.h1 * rho + D.k1 * E;
+    const R fr = D.a2 + D.h2 * rho + D.k2 * E;
+    // Delta_k / D_k for the even non-conserved moments
+    const R aeps = D.s_eps * (eps - (D.c_er * rho + D.c_eE * E)) * R(1.0 / 42196.0);
+    const R avp = D.s_vp * (vp - (D.c_vr * rho + D.c_vE * E)) * R(1.0 / 548.0);
+    const R aXX = D.s_XX * (XX - (jx * jx - jy * jy) * inv_rho) * R(1.0 / 68.0);
+    const R aXY = D.s_XX * (XY - jx * jy * inv_rho) * R(0.25);
+    const R aXXe = D.s_XXe * XXe * R(1.0 / 68.0);
+    // odd moments: the force enters as Delta_j = -F
+    const R Fx = D.F0x + D.gx * rho, Fy = D.F0y + D.gy * rho;
+    const R bjx = -Fx * R(1.0 / 14.0), bjy = -Fy * R(1.0 / 14.0);
+    const R bqx = D.s_q * (qx - jx * fq) * R(0.05), bqy = D.s_q * (qy - jy * fq) * R(0.05);
+    const R brx = D.s_r * (rx - jx * fr) * R(1.0 / 70.0), bry = D.s_r * (ry - jy * fr) * R(1.0 / 70.0);
+
+    const R e0 = R(140) * aeps - R(12) * avp;
+    const R ec1 = R(-2) * aeps + R(8) * avp;
+    const R e1 = ec1 + aXX - R(4) * aXXe;
+    const R e2 = ec1 - aXX + R(4) * aXXe;
+    const R ec5 = R(-67) * aeps - R(6) * avp;
+    const R e5 = ec5 + aXY;
+    const R e6 = ec5 - aXY;
+    const R ec9 = R(34) * aeps + avp;
+    const R e9 = ec9 + R(4) * aXX + aXXe;
+    const R e10 = ec9 - R(4) * aXX - aXXe;
+    const R o1 = bjx - R(2) * bqx + R(4) * brx;
+    const R o2 = bjy - R(2) * bqy + R(4) * bry;
+    const R o5 = bjx + bjy - bqx - bqy - R(3) * (brx + bry);
+    const R o6 = -bjx + bjy + bqx - bqy + R(3) * (brx - bry);
+    const R o9 = R(2) * (bjx + bqx) + brx;
+    const R o10 = R(2) * (bjy + bqy) + bry;
+
+    g[0] -= e0;
+    g[1] -= e1 + o1;
+    g[3] -= e1 - o1;
+    g[2] -= e2 + o2;
+    g[4] -= e2 - o2;
+    g[5] -= e5 + o5;
+    g[7] -= e5 - o5;
+    g[6] -= e6 + o6;
+    g[8] -= e6 - o6;
+    g[9] -= e9 + o9;
+    g[11] -= e9 - o9;
+    g[10] -= e10 + o10;
+    g[12] -= e10 - o10;
+}
+
+// ---------------------------------------------------------------------------
+// Gather for a node whose 13 sources are all inside the domain or across a
+// periodic side.
+template <typename R>
+__device__ __forceinline__ void gather_bulk(const R* __restrict__ b, const Dom<R>& D, int x, int y, R g[13]) {
+    const int P = D.pitch, S = D.plane;
+    int xm1 = x - 1, xm2 = x - 2, xp1 = x + 1, xp2 = x + 2;
+    int ym1 = y - 1, ym2 = y - 2, yp1 = y + 1, yp2 = y + 2;
+    if (D.xper) {
+        xm1 = wrap(xm1, D.nx); xm2 = wrap(xm2, D.nx); xp1 = wrap(xp1, D.nx); xp2 = wrap(xp2, D.nx);
+    }
+    if (D.yper) {
+        ym1 = wrap(ym1, D.ny); ym2 = wrap(ym2, D.ny); yp1 = wrap(yp1, D.ny); yp2 = wrap(yp2, D.ny);
+    }
+    const int r0 = y * P, rm1 = ym1 * P, rm2 = ym2 * P, rp1 = yp1 * P, rp2 = yp2 * P;
+    g[0] = b[r0 + x];
+    g[1] = b[1 * S + r0 + xm1];
+    g[2] = b[2 * S + rm1 + x];
+    g[3] = b[3 * S + r0 + xp1];
+    g[4] = b[4 * S + rp1 + x];
+    g[5] = b[5 * S + rm1 + xm1];
+    g[6] = b[6 * S + rm1 + xp1];
+    g[7] = b[7 * S + rp1 + xp1];
+    g[8] = b[8 * S + rp1 + xm1];
+    g[9] = b[9 * S + r0 + xm2];
+    g[10] = b[10 * S + rm2 + x];
+    g[11] = b[11 * S + r0 + xp2];
+    g[12] = b[12 * S + rp2 + x];
+}
+
+// Deviation moments rho' and E' of one stored node.
+template <typename R>
+__device__ __forceinline__ void node_rho_E(const R* __restrict__ b, const Dom<R>& D, int c, R& rho, R& E) {
+    R r = R(0), e = R(0);
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        const R v = b[i * D.plane + c];
+        r += v;
+        e += R(c_M[1][i]) * v;
+    }
+    rho = r;
+    E = e;
+}
+
+// Equilibrium moments (deviation from rest) of wall w on the wall-normal line
+// through (x, y), from the time-t state: rho_W = (3 rho_0 - rho_1)/2 of the
+// first two fluid layers, j_W = rho_W u_W along the wall, E_W imposed
+// (temperature wall) or E of layer 0 (adiabatic wall); sec. 7.
+template <typename R>
+__device__ void wall_moments(const R* __restrict__ b, const Dom<R>& D, int w, int x, int y, R m[13]) {
+    int c0, c1;
+    if (w == 0) { c0 = y * D.pitch; c1 = c0 + 1; }
+    else if (w == 1) { c0 = y * D.pitch + D.nx - 1; c1 = c0 - 1; }
+    else if (w == 2) { c0 = x; c1 = D.pitch + x; }
+    else { c0 = (D.ny - 1) * D.pitch + x; c1 = c0 - D.pitch; }
+    R r0, e0, r1, e1;
+    node_rho_E(b, D, c0, r0, e0);
+    node_rho_E(b, D, c1, r1, e1);
+    const R rho = R(1.5) * r0 - R(0.5) * r1;
+    const R E = (D.kind[w] == kDirichletT) ? D.wall_dE[w] : e0;
+    const R rhoW = R(1) + rho;
+    const R jt = rhoW * D.wall_u[w];
+    const R jx = (w < 2) ? R(0) : jt;
+    const R jy = (w < 2) ? jt : R(0);
+    const R fq = D.a1 + D.h1 * rho + D.k1 * E;
+    const R fr = D.a2 + D.h2 * rho + D.k2 * E;
+    m[0] = rho;
+    m[1] = E;
+    m[2] = D.c_er * rho + D.c_eE * E;
+    m[3] = D.c_vr * rho + D.c_vE * E;
+    m[4] = jx;
+    m[5] = jy;
+    m[6] = jx * fq;
+    m[7] = jy * fq;
+    m[8] = jx * fr;
+    m[9] = jy * fr;
+    m[10] = (jx * jx - jy * jy) / rhoW;
+    m[11] = jx * jy / rhoW;
+    m[12] = R(0);
+}
+
+// Gather for a node within two nodes of a wall: links whose source lies beyond
+// a wall come back along their reversed path from x' (tangential coordinate of
+// x kept, normal coordinate reflected through the wall), with
+//   bounce-back:      g_i = g*_opp(x') + 2 sum_{k odd}  M_ki m_k(W) / D_k
+//   anti-bounce-back: g_i = -g*_opp(x') + 2 sum_{k even} M_ki m_k(W) / D_k
+// (eq d2q13-cl-abb; deviations, since f^rest is even in v).  When a diagonal
+// source lies beyond two walls, the West/East wall applies.
+template <typename R>
+__device__ void gather_wall(const R* __restrict__ b, const Dom<R>& D, int x, int y, R g[13]) {
+    const int P = D.pitch, S = D.plane;
+    R mw[2][13];
+    bool have[2] = {false, false};
+    int widx[2] = {-1, -1};
+#pragma unroll 1
+    for (int i = 0; i < 13; ++i) {
+        const int vx = c_vx[i], vy = c_vy[i];
+        int sx = x - vx, sy = y - vy;
+        int w = -1;
+        if (D.xper) sx = wrap(sx, D.nx);
+        else if (sx < 0) w = 0;
+        else if (sx >= D.nx) w = 1;
+        if (D.yper) sy = wrap(sy, D.ny);
+        else if (w < 0 && sy < 0) w = 2;
+        else if (w < 0 && sy >= D.ny) w = 3;
+        if (w < 0) {
+            g[i] = b[i * S + sy * P + sx];
+            continue;
+        }
+        int px = x, py = y;
+        if (w == 0) px = -1 + vx - x;
+        else if (w == 1) px = 2 * D.nx - 1 + vx - x;
+        else if (w == 2) py = -1 + vy - y;
+        else py = 2 * D.ny - 1 + vy - y;
+        const R src = b[c_opp[i] * S + py * P + px];
+        const int slot = (w < 2) ? 0 : 1;
+        if (!have[slot] || widx[slot] != w) {
+            wall_moments(b, D, w, x, y, mw[slot]);
+            have[slot] = true;
+            widx[slot] = w;
+        }
+        const bool normal = (w < 2) ? (vy == 0) : (vx == 0);
+        const bool abb = normal && D.kind[w] == kDirichletT;
+        R extra = R(0);
+#pragma unroll
+        for (int k = 0; k < 13; ++k) {
+            const bool odd = (k >= 4 && k <= 9);
+            if (abb != odd) extra += R(c_M[k][i]) * mw[slot][k] / R(c_D[k]);
+        }
+        g[i] = (abb ? -src : src) + R(2) * extra;
+    }
+}
+
+// XCD-aware block order: the hardware deals consecutive workgroups round-robin
+// to the 8 XCDs; this remap gives each XCD a contiguous run of tiles so the
+// shifted reads of neighbouring tiles hit the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int per = nb >> 3, rem = nb & 7;
+    const int xcd = b & 7, local = b >> 3;
+    return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+template <typename R>
+__device__ __forceinline__ void store_node(R* __restrict__ b, int S, int c, const R g[13]) {
+#pragma unroll
+    for (int i = 0; i < 13; ++i) __builtin_nontemporal_store(g[i], &b[i * S + c]);
+}
+
+// One step over a list of tiles.  TX nodes per row, 256/TX rows per pass, RPT
+// passes per tile.  WALLS = false: every node is bulk (tiles at least two nodes
+// from any wall); WALLS = true: per-node choice between bulk and wall gather.
+template <typename R, int TX, int RPT, bool WALLS>
+__global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R* __restrict__ dst,
+                                                   const Dom<R>* __restrict__ doms,
+                                                   const Tile* __restrict__ tiles, int ntiles) {
+    constexpr int TYB = 256 / TX;
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const Tile tl = tiles[t];
+    const Dom<R>& D = doms[tl.dom];
+    const R* __restrict__ a = src + D.off;
+    R* __restrict__ o = dst + D.off;
+    const int x = tl.x0 + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int y = tl.y0 + threadIdx.y + r * TYB;
+        if (x >= D.nx || y >= D.ny) continue;
+        R g[13];
+        if (WALLS) {
+            const bool near = (!D.xper && (x < 2 || x >= D.nx - 2)) || (!D.yper && (y < 2 || y >= D.ny - 2));
+            if (near) gather_wall(a, D, x, y, g);
+            else gather_bulk(a, D, x, y, g);
+        } else {
+            gather_bulk(a, D, x, y, g);
+        }
+        if (D.collide) collide(g, D);
+        store_node(o, D.plane, y * D.pitch + x, g);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: g = f^eq(rho, j = rho u, E = T + 13/2 |u|^2) - f^rest, built in
+// FP64 from the equilibrium moments (eq d2q13-moments-equil) and M^T D^-1, then
+// one collision in the working precision.
+template <typename R>
+__global__ __launch_bounds__(256) void init_kernel(R* __restrict__ dst, const Dom<R>* __restrict__ doms, int d,
+                                                   const double* __restrict__ rho_in,
+                                                   const double* __restrict__ ux_in,
+                                                   const double* __restrict__ uy_in,
+                                                   const double* __restrict__ T_in,
+                                                   const double* __restrict__ coef /* c_er c_eE c_vr c_vE a1 h1 k1 a2 h2 k2 */) {
+    const Dom<R>& D = doms[d];
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= D.nx || y >= D.ny) return;
+    const int n = y * D.nx + x;
+    const double rho = rho_in[n], ux = ux_in[n], uy = uy_in[n];
+    const double E = T_in[n] + 6.5 * (ux * ux + uy * uy);
+    const double rp = rho - 1.0, Ep = E - D.E0;
+    const double jx = rho * ux, jy = rho * uy;
+    double m[13];
+    m[0] = rp;
+    m[1] = Ep;
+    m[2] = coef[0] * rp + coef[1] * Ep;
+    m[3] = coef[2] * rp + coef[3] * Ep;
+    m[4] = jx;
+    m[5] = jy;
+    const double fq = coef[4] + coef[5] * rp + coef[6] * Ep;
+    const double fr = coef[7] + coef[8] * rp + coef[9] * Ep;
+    m[6] = jx * fq;
+    m[7] = jy * fq;
+    m[8] = jx * fr;
+    m[9] = jy * fr;
+    m[10] = (jx * jx - jy * jy) / rho;
+    m[11] = jx * jy / rho;
+    m[12] = 0.0;
+    R g[13];
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 13; ++k) s += double(c_M[k][i]) * m[k] / double(c_D[k]);
+        g[i] = R(s);
+    }
+    if (D.collide) collide(g, D);
+    R* __restrict__ o = dst + D.off;
+#pragma unroll
+    for (int i = 0; i < 13; ++i) o[i * D.plane + y * D.pitch + x] = g[i];
+}
+
+// ---------------------------------------------------------------------------
+// Read-back at time t from the kept f*(t): rho = 1 + sum g, E = E0 + sum M_E g,
+// j = j* - F, u = (j + F/2)/rho = (j* - F/2)/rho, T = E - 13/2 |u|^2 (sec. 7).
+template <typename R>
+__device__ __forceinline__ void node_macro(const R* __restrict__ a, const Dom<R>& D, int c, double& rho, double& ux,
+                                           double& uy, double& T) {
+    double r = 0.0, e = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        const double v = double(a[i * D.plane + c]);
+        r += v;
+        e += double(c_M[1][i]) * v;
+        jx += double(c_vx[i]) * v;
+        jy += double(c_vy[i]) * v;
+    }
+    const double Fx = D.F0x_d + D.gx_d * r, Fy = D.F0y_d + D.gy_d * r;
+    rho = 1.0 + r;
+    ux = (jx - 0.5 * Fx) / rho;
+    uy = (jy - 0.5 * Fy) / rho;
+    T = D.E0 + e - 6.5 * (ux * ux + uy * uy);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void moments_kernel(const R* __restrict__ src, const Dom<R>* __restrict__ doms,
+                                                      int d, double* __restrict__ rho_out,
+                                                      double* __restrict__ ux_out, double* __restrict__ uy_out,
+                                                      double* __restrict__ T_out) {
+    const Dom<R>& D = doms[d];
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= D.nx || y >= D.ny) return;
+    double rho, ux, uy, T;
+    node_macro(src + D.off, D, y * D.pitch + x, rho, ux, uy, T);
+    const int n = y * D.nx + x;
+    if (rho_out) rho_out[n] = rho;
+    if (ux_out) ux_out[n] = ux;
+    if (uy_out) uy_out[n] = uy;
+    if (T_out) T_out[n] = T;
+}
+
+// State copy-out (absolute FP64 f*) and copy-in.
+template <typename R>
+__global__ __launch_bounds__(256) void get_state_kernel(const R* __restrict__ src, const Dom<R>* __restrict__ doms,
+                                                        int d, double* __restrict__ out) {
+    const Dom<R>& D = doms[d];
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= D.nx || y >= D.ny) return;
+    const long long n = (long long)D.nx * D.ny;
+#pragma unroll
+    for (int i = 0; i < 13; ++i)
+        out[i * n + y * D.nx + x] = double(src[D.off + i * D.plane + y * D.pitch + x]) + D.frest[c_cls[i]];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void set_state_kernel(R* __restrict__ dst, const Dom<R>* __restrict__ doms, int d,
+                                                        const double* __restrict__ in) {
+    const Dom<R>& D = doms[d];
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= D.nx || y >= D.ny) return;
+    const long long n = (long long)D.nx * D.ny;
+#pragma unroll
+    for (int i = 0; i < 13; ++i)
+        dst[D.off + i * D.plane + y * D.pitch + x] = R(in[i * n + y * D.nx + x] - D.frest[c_cls[i]]);
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics, pass 1: one partial record per tile (FP64), in the order of the
+// domain-ordered tile table; pass 2 reduces each domain's records in order, so
+// results do not depend on scheduling.
+//   part[0..3] sum rho', jx, jy, E'     part[4] heat flux (face crossing, see header)
+//   part[5] max |u|  part[6] max |u(x) + u(xbar)|  part[7] non-finite count
+//   part[8] min rho
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename R, int TX, int RPT>
+__global__ __launch_bounds__(256) void diag_partial_kernel(const R* __restrict__ src, const Dom<R>* __restrict__ doms,
+                                                           const Tile* __restrict__ tiles,
+                                                           double* __restrict__ part) {
+    constexpr int TYB = 256 / TX;
+    const int t = blockIdx.x;
+    const Tile tl = tiles[t];
+    const Dom<R>& D = doms[tl.dom];
+    const R* __restrict__ a = src + D.off;
+    double acc[5] = {0, 0, 0, 0, 0};
+    double umax = 0.0, asym = 0.0, nonfin = 0.0, rmin = INFINITY;
+    const int flo = D.xper ? 0 : 1, fhi = D.xper ? D.nx - 1 : D.nx - 3;
+    const int x = tl.x0 + threadIdx.x;
+    for (int r = 0; r < RPT; ++r) {
+        const int y = tl.y0 + threadIdx.y + r * TYB;
+        if (x >= D.nx || y >= D.ny) continue;
+        const int c = y * D.pitch + x;
+        double rp = 0, e = 0, jx = 0, jy = 0, heat = 0;
+#pragma unroll
+        for (int i = 0; i < 13; ++i) {
+            const R vr = a[i * D.plane + c];
+            if (!isfinite(double(vr))) nonfin += 1.0;
+            const double v = double(vr);
+            rp += v;
+            e += double(c_M[1][i]) * v;
+            jx += double(c_vx[i]) * v;
+            jy += double(c_vy[i]) * v;
+            const int vx = c_vx[i];
+            int cnt = 0;
+            if (D.xper) {
+                cnt = vx;
+            } else if (vx > 0) {
+                for (int xf = x; xf < x + vx; ++xf) cnt += (xf >= flo && xf <= fhi);
+            } else if (vx < 0) {
+                for (int xf = x + vx; xf < x; ++xf) cnt -= (xf >= flo && xf <= fhi);
+            }
+            heat += (double(c_M[1][i]) - D.B) * double(cnt) * (v + D.frest[c_cls[i]]);
+        }
+        const double Fx = D.F0x_d + D.gx_d * rp, Fy = D.F0y_d + D.gy_d * rp;
+        acc[0] += rp;
+        acc[1] += jx - Fx;
+        acc[2] += jy - Fy;
+        acc[3] += e;
+        acc[4] += heat;
+        const double rho = 1.0 + rp;
+        const double ux = (jx - 0.5 * Fx) / rho, uy = (jy - 0.5 * Fy) / rho;
+        umax = fmax(umax, sqrt(ux * ux + uy * uy));
+        rmin = fmin(rmin, rho);
+        double rb, uxb, uyb, Tb;
+        node_macro(a, D, (D.ny - 1 - y) * D.pitch + (D.nx - 1 - x), rb, uxb, uyb, Tb);
+        const double sx = ux + uxb, sy = uy + uyb;
+        asym = fmax(asym, sqrt(sx * sx + sy * sy));
+    }
+    __shared__ double red[4][9];
+    const int lane = (threadIdx.y * TX + threadIdx.x) & 63;
+    const int wave = (threadIdx.y * TX + threadIdx.x) >> 6;
+    double vals[9];
+    for (int k = 0; k < 5; ++k) vals[k] = wave_sum(acc[k]);
+    vals[5] = wave_max(umax);
+    vals[6] = wave_max(asym);
+    vals[7] = wave_sum(nonfin);
+    vals[8] = wave_min(rmin);
+    if (lane == 0)
+        for (int k = 0; k < 9; ++k) red[wave][k] = vals[k];
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        double out[9];
+        for (int k = 0; k < 9; ++k) out[k] = red[0][k];
+        for (int w = 1; w < 4; ++w) {
+            for (int k = 0; k < 5; ++k) out[k] += red[w][k];
+            out[5] = fmax(out[5], red[w][5]);
+            out[6] = fmax(out[6], red[w][6]);
+            out[7] += red[w][7];
+            out[8] = fmin(out[8], red[w][8]);
+        }
+        for (int k = 0; k < 9; ++k) part[t * kDiagPartials + k] = out[k];
+    }
+}
+
+// Pass 2: one thread per domain walks its partial records in order.
+template <typename R>
+__global__ void diag_final_kernel(const Dom<R>* __restrict__ doms, int ndom, const double* __restrict__ part,
+                                  double* __restrict__ out) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= ndom) return;
+    const Dom<R>& D = doms[d];
+    double s[5] = {0, 0, 0, 0, 0};
+    double umax = 0.0, asym = 0.0, nonfin = 0.0, rmin = INFINITY;
+    for (int t = D.tile0; t < D.tile0 + D.ntiles; ++t) {
+        const double* p = part + t * kDiagPartials;
+        for (int k = 0; k < 5; ++k) s[k] += p[k];
+        umax = fmax(umax, p[5]);
+        asym = fmax(asym, p[6]);
+        nonfin += p[7];
+        rmin = fmin(rmin, p[8]);
+    }
+    const double N = double(D.nx) * double(D.ny);
+    const int faces = D.xper ? D.nx : D.nx - 3;
+    double* o = out + d * kDiagOut;
+    o[0] = N + s[0];
+    o[1] = s[1];
+    o[2] = s[2];
+    o[3] = N * D.E0 + s[3];
+    o[4] = s[4];
+    o[5] = (faces > 0) ? s[4] / (double(faces) * D.ny) * D.nu_scale : 0.0;
+    o[6] = umax;
+    o[7] = asym;
+    o[8] = umax > 0.0 ? asym / umax : 0.0;
+    o[9] = nonfin;
+    o[10] = rmin;
+    for (int k = 11; k < kDiagOut; ++k) o[k] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers (called from lbm13_capi.cpp).
+
+template <typename R, int TX, int RPT>
+static hipError_t launch_step_t(const R* src, R* dst, const Dom<R>* doms, const Tile* bulk, int nbulk,
+                                const Tile* edge, int nedge, hipStream_t s) {
+    constexpr dim3 blk(TX, 256 / TX);
+    if (nbulk > 0) step_kernel<R, TX, RPT, false><<<nbulk, blk, 0, s>>>(src, dst, doms, bulk, nbulk);
+    if (nedge > 0) step_kernel<R, TX, RPT, true><<<nedge, blk, 0, s>>>(src, dst, doms, edge, nedge);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_step(int tile_x, int tile_y, const R* src, R* dst, const Dom<R>* doms, const Tile* bulk,
+                       int nbulk, const Tile* edge, int nedge, hipStream_t s) {
+    if (tile_x == 64 && tile_y == 4) return launch_step_t<R, 64, 1>(src, dst, doms, bulk, nbulk, edge, nedge, s);
+    if (tile_x == 64 && tile_y == 8) return launch_step_t<R, 64, 2>(src, dst, doms, bulk, nbulk, edge, nedge, s);
+    if (tile_x == 64 && tile_y == 16) return launch_step_t<R, 64, 4>(src, dst, doms, bulk, nbulk, edge, nedge, s);
+    if (tile_x == 32 && tile_y == 8) return launch_step_t<R, 32, 1>(src, dst, doms, bulk, nbulk, edge, nedge, s);
+    if (tile_x == 32 && tile_y == 16) return launch_step_t<R, 32, 2>(src, dst, doms, bulk, nbulk, edge, nedge, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_diag(int tile_x, int tile_y, const R* src, const Dom<R>* doms, int ndom, const Tile* all,
+                       int nall, double* part, double* out, hipStream_t s) {
+    if (nall > 0) {
+        if (tile_x == 64) {
+            const dim3 blk(64, 4);
+            if (tile_y == 4) diag_partial_kernel<R, 64, 1><<<nall, blk, 0, s>>>(src, doms, all, part);
+            else if (tile_y == 8) diag_partial_kernel<R, 64, 2><<<nall, blk, 0, s>>>(src, doms, all, part);
+            else diag_partial_kernel<R, 64, 4><<<nall, blk, 0, s>>>(src, doms, all, part);
+        } else {
+            const dim3 blk(32, 8);
+            if (tile_y == 8) diag_partial_kernel<R, 32, 1><<<nall, blk, 0, s>>>(src, doms, all, part);
+            else diag_partial_kernel<R, 32, 2><<<nall, blk, 0, s>>>(src, doms, all, part);
+        }
+    }
+    diag_final_kernel<R><<<(ndom + 63) / 64, 64, 0, s>>>(doms, ndom, part, out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_init(int nx, int ny, R* dst, const Dom<R>* doms, int d, const double* rho, const double* ux,
+                       const double* uy, const double* T, const double* coef, hipStream_t s) {
+    const dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
+    init_kernel<R><<<grd, blk, 0, s>>>(dst, doms, d, rho, ux, uy, T, coef);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_moments(int nx, int ny, const R* src, const Dom<R>* doms, int d, double* rho, double* ux,
+                          double* uy, double* T, hipStream_t s) {
+    const dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
+    moments_kernel<R><<<grd, blk, 0, s>>>(src, doms, d, rho, ux, uy, T);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_get_state(int nx, int ny, const R* src, const Dom<R>* doms, int d, double* out, hipStream_t s) {
+    const dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
+    get_state_kernel<R><<<grd, blk, 0, s>>>(src, doms, d, out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, const double* in, hipStream_t s) {
+    const dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
+    set_state_kernel<R><<<grd, blk, 0, s>>>(dst, doms, d, in);
+    return hipGetLastError();
+}
+
+#define LBM13_INSTANTIATE(R)                                                                                      \
+    template hipError_t launch_step<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, \
+                                       hipStream_t);                                                              \
+    template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*,         \
+                                       double*, hipStream_t);                                                     \
+    template hipError_t launch_init<R>(int, int, R*, const Dom<R>*, int, const double*, const double*,           \
+                                       const double*, const double*, const double*, hipStream_t);                 \
+    template hipError_t launch_moments<R>(int, int, const R*, const Dom<R>*, int, double*, double*, double*,     \
+                                          double*, hipStream_t);                                                  \
+    template hipError_t launch_get_state<R>(int, int, const R*, const Dom<R>*, int, double*, hipStream_t);        \
+    template hipError_t launch_set_state<R>(int, int, R*, const Dom<R>*, int, const double*, hipStream_t);
+
+LBM13_INSTANTIATE(double)
+LBM13_INSTANTIATE(float)
+
+}  // namespace lbm13

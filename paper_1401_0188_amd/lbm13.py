@@ -1,0 +1,364 @@
+"""Thin ctypes binding of liblbm13.so (C ABI in include/lbm13.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  PyTorch provides the device workspace and the stream.  There is
+no CPU fallback: if the library is missing or no GPU is present the calls
+raise.
+
+Two layers:
+  * ``lib()``: the raw ctypes handle with the C names (``lbm13_create`` ...).
+  * ``Lattice`` / ``Batch``: owners of a context whose methods carry the same
+    names without the ``lbm13_`` / ``lbm13_batch_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm13.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE_PARAMS, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32_DEV = 0, 1
+PERIODIC, WALL_ADIABATIC, WALL_DIRICHLET_T = 0, 1, 2
+WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
+DIAG_NAMES = ("sum_rho", "sum_jx", "sum_jy", "sum_E", "heat_flux", "Nu_mean", "u_max", "asym_abs",
+              "asym_rel", "nonfinite", "rho_min")
+TILE_SHAPES = ((64, 4), (64, 8), (64, 16), (32, 8), (32, 16))
+
+
+class LBM13Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("lbm13 error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Side(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("u_tangential", ctypes.c_double), ("T_wall", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("s_XX", ctypes.c_double), ("s_rx", ctypes.c_double), ("s_eps", ctypes.c_double),
+                ("s_varpi", ctypes.c_double), ("s_XXe", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("E0", ctypes.c_double), ("c1", ctypes.c_double),
+                ("k2", ctypes.c_double), ("c_epsE", ctypes.c_double), ("c_varpi_rho", ctypes.c_double),
+                ("c_varpi_E", ctypes.c_double),
+                ("F0", ctypes.c_double * 2), ("g", ctypes.c_double * 2), ("rho0", ctypes.c_double),
+                ("collide", ctypes.c_int)]
+
+
+class Derived(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "A", "Y", "h1", "k1", "h2", "c2", "c_eps_rho", "sigma_XX", "sigma_q", "s_q",
+        "nu", "kappa", "cs2", "B", "kappa_E")]
+
+
+# Free-parameter set used by default (the paper prints none; chosen by a
+# linear-stability scan of the dispersion relation, as the paper describes).
+DEFAULT_PARAMS = dict(s_XX=1.6, s_rx=1.05, s_eps=1.0, s_varpi=1.0, s_XXe=1.5, Pr=0.71, E0=-2.0, c1=-3.0,
+                      k2=-2.5, c_epsE=-2.5, c_varpi_rho=-6.0, c_varpi_E=-0.5, F0=(0.0, 0.0), g=(0.0, 0.0),
+                      rho0=1.0, collide=1)
+
+_lib = None
+
+
+def lib():
+    """Load liblbm13.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblbm13.so is not built: run `python -m paper_1401_0188_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p
+    sz, i32, i64 = ctypes.c_size_t, ctypes.c_int, ctypes.c_longlong
+    P, S, D = ctypes.POINTER(Params), ctypes.POINTER(Side), ctypes.POINTER(Derived)
+    sig = {
+        "lbm13_derive": (i32, [P, D]),
+        "lbm13_workspace_bytes": (sz, [i32, i32, i32]),
+        "lbm13_create": (i32, [i32, i32, i32, vp, sz, vp, ctypes.POINTER(vp)]),
+        "lbm13_set_params": (i32, [vp, P, S, D]),
+        "lbm13_init_moments": (i32, [vp, dp, dp, dp, dp]),
+        "lbm13_step": (i32, [vp, i64]),
+        "lbm13_moments": (i32, [vp, dp, dp, dp, dp]),
+        "lbm13_diagnostics": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "lbm13_get_state": (i32, [vp, dp]),
+        "lbm13_set_state": (i32, [vp, dp]),
+        "lbm13_steps_done": (i64, [vp]),
+        "lbm13_set_tile": (i32, [vp, i32, i32]),
+        "lbm13_autotune": (i32, [vp, i32, ip, ip]),
+        "lbm13_use_graph": (i32, [vp, i32]),
+        "lbm13_destroy": (i32, [vp]),
+        "lbm13_last_error": (ctypes.c_char_p, [vp]),
+        "lbm13_batch_workspace_bytes": (sz, [i32, ip, ip, i32]),
+        "lbm13_batch_create": (i32, [i32, ip, ip, i32, vp, sz, vp, ctypes.POINTER(vp)]),
+        "lbm13_batch_set_params": (i32, [vp, i32, P, S, D]),
+        "lbm13_batch_init_moments": (i32, [vp, i32, dp, dp, dp, dp]),
+        "lbm13_batch_step": (i32, [vp, i64]),
+        "lbm13_batch_moments": (i32, [vp, i32, dp, dp, dp, dp]),
+        "lbm13_batch_diagnostics": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "lbm13_batch_get_state": (i32, [vp, i32, dp]),
+        "lbm13_batch_set_state": (i32, [vp, i32, dp]),
+        "lbm13_batch_set_tile": (i32, [vp, i32, i32]),
+        "lbm13_batch_autotune": (i32, [vp, i32, ip, ip]),
+        "lbm13_batch_use_graph": (i32, [vp, i32]),
+        "lbm13_batch_nodes": (i64, [vp]),
+        "lbm13_batch_destroy": (i32, [vp]),
+        "lbm13_batch_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def make_params(**kw) -> Params:
+    d = dict(DEFAULT_PARAMS)
+    for k, v in kw.items():
+        if k not in d:
+            raise KeyError("unknown parameter %r" % k)
+        d[k] = v
+    p = Params()
+    for k, v in d.items():
+        if k in ("F0", "g"):
+            getattr(p, k)[0], getattr(p, k)[1] = float(v[0]), float(v[1])
+        elif k == "collide":
+            p.collide = int(v)
+        else:
+            setattr(p, k, float(v))
+    return p
+
+
+def make_sides(kinds=(PERIODIC,) * 4, u_t=(0.0,) * 4, T_w=(0.0,) * 4):
+    arr = (Side * 4)()
+    for w in range(4):
+        arr[w].kind = int(kinds[w])
+        arr[w].u_tangential = float(u_t[w])
+        arr[w].T_wall = float(T_w[w])
+    return arr
+
+
+def derive(**kw):
+    """Host-side derived coefficients; returns (status, dict)."""
+    d = Derived()
+    st = lib().lbm13_derive(ctypes.byref(make_params(**kw)), ctypes.byref(d))
+    return st, {n: getattr(d, n) for n, _ in Derived._fields_}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("lbm13 needs a GPU: torch.cuda.is_available() is False")
+    return torch
+
+
+def _dev_f64(a, torch, n):
+    t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64) if not isinstance(a, torch.Tensor) else a,
+                        dtype=torch.float64, device="cuda").contiguous()
+    if t.numel() != n:
+        raise ValueError("field has %d values, expected %d" % (t.numel(), n))
+    return t
+
+
+class _Base:
+    _prefix = ""
+
+    def _check(self, st):
+        if st != OK:
+            msg = getattr(lib(), self._prefix + "last_error")(self._h)
+            raise LBM13Error(st, (msg or b"").decode())
+        return st
+
+
+class Lattice(_Base):
+    """One nx x ny domain (owns its workspace tensor and context)."""
+
+    _prefix = "lbm13_"
+
+    def __init__(self, nx: int, ny: int, precision: int = FP64, stream=None):
+        torch = _torch()
+        L = lib()
+        self.nx, self.ny, self.precision = int(nx), int(ny), int(precision)
+        nbytes = L.lbm13_workspace_bytes(self.nx, self.ny, self.precision)
+        if nbytes == 0:
+            raise LBM13Error(EINVAL, "invalid size or precision")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = L.lbm13_create(self.nx, self.ny, self.precision, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise LBM13Error(st, "lbm13_create failed")
+        self._h = h
+        self.derived = None
+        self._keep = []
+
+    def set_params(self, sides=None, **kw):
+        d = Derived()
+        self._check(lib().lbm13_set_params(self._h, ctypes.byref(make_params(**kw)),
+                                           sides if sides is not None else make_sides(), ctypes.byref(d)))
+        self.derived = {n: getattr(d, n) for n, _ in Derived._fields_}
+        return self.derived
+
+    def init_moments(self, rho, ux, uy, T):
+        torch = _torch()
+        n = self.nx * self.ny
+        f = [_dev_f64(a, torch, n) for a in (rho, ux, uy, T)]
+        self._keep = f  # kept alive until the next init (the kernel is async)
+        self._check(lib().lbm13_init_moments(self._h, *[ctypes.c_void_p(t.data_ptr()) for t in f]))
+
+    def step(self, n: int = 1):
+        self._check(lib().lbm13_step(self._h, int(n)))
+
+    def moments(self):
+        torch = _torch()
+        out = [torch.empty((self.ny, self.nx), dtype=torch.float64, device="cuda") for _ in range(4)]
+        self._check(lib().lbm13_moments(self._h, *[ctypes.c_void_p(t.data_ptr()) for t in out]))
+        return tuple(out)
+
+    def diagnostics(self, check: bool = True):
+        out = (ctypes.c_double * 16)()
+        st = lib().lbm13_diagnostics(self._h, out)
+        if check:
+            self._check(st)
+        return dict(zip(DIAG_NAMES, list(out)[:len(DIAG_NAMES)]))
+
+    def get_state(self):
+        torch = _torch()
+        out = torch.empty((13, self.ny, self.nx), dtype=torch.float64, device="cuda")
+        self._check(lib().lbm13_get_state(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def set_state(self, src):
+        torch = _torch()
+        t = _dev_f64(src, torch, 13 * self.nx * self.ny)
+        self._keep = [t]
+        self._check(lib().lbm13_set_state(self._h, ctypes.c_void_p(t.data_ptr())))
+
+    def steps_done(self) -> int:
+        return int(lib().lbm13_steps_done(self._h))
+
+    def set_tile(self, tile_x: int, tile_y: int):
+        self._check(lib().lbm13_set_tile(self._h, int(tile_x), int(tile_y)))
+
+    def autotune(self, steps: int = 20):
+        tx, ty = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().lbm13_autotune(self._h, int(steps), ctypes.byref(tx), ctypes.byref(ty)))
+        return tx.value, ty.value
+
+    def use_graph(self, k: int):
+        self._check(lib().lbm13_use_graph(self._h, int(k)))
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().lbm13_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch(_Base):
+    """Many independent domains advanced by one launch per step."""
+
+    _prefix = "lbm13_batch_"
+
+    def __init__(self, sizes, precision: int = FP32_DEV, stream=None):
+        torch = _torch()
+        L = lib()
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        self.count = len(self.sizes)
+        self.precision = int(precision)
+        nx = (ctypes.c_int * self.count)(*[s[0] for s in self.sizes])
+        ny = (ctypes.c_int * self.count)(*[s[1] for s in self.sizes])
+        nbytes = L.lbm13_batch_workspace_bytes(self.count, nx, ny, self.precision)
+        if nbytes == 0:
+            raise LBM13Error(EINVAL, "invalid sizes or precision")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = L.lbm13_batch_create(self.count, nx, ny, self.precision, ctypes.c_void_p(self.workspace.data_ptr()),
+                                  nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise LBM13Error(st, "lbm13_batch_create failed")
+        self._h = h
+        self.derived = [None] * self.count
+        self._keep = {}
+
+    def set_params(self, i: int, sides=None, **kw):
+        d = Derived()
+        self._check(lib().lbm13_batch_set_params(self._h, int(i), ctypes.byref(make_params(**kw)),
+                                                 sides if sides is not None else make_sides(), ctypes.byref(d)))
+        self.derived[i] = {n: getattr(d, n) for n, _ in Derived._fields_}
+        return self.derived[i]
+
+    def init_moments(self, i: int, rho, ux, uy, T):
+        torch = _torch()
+        nx, ny = self.sizes[i]
+        f = [_dev_f64(a, torch, nx * ny) for a in (rho, ux, uy, T)]
+        self._keep[i] = f
+        self._check(lib().lbm13_batch_init_moments(self._h, int(i), *[ctypes.c_void_p(t.data_ptr()) for t in f]))
+
+    def step(self, n: int = 1):
+        self._check(lib().lbm13_batch_step(self._h, int(n)))
+
+    def moments(self, i: int):
+        torch = _torch()
+        nx, ny = self.sizes[i]
+        out = [torch.empty((ny, nx), dtype=torch.float64, device="cuda") for _ in range(4)]
+        self._check(lib().lbm13_batch_moments(self._h, int(i), *[ctypes.c_void_p(t.data_ptr()) for t in out]))
+        return tuple(out)
+
+    def diagnostics(self, check: bool = True):
+        out = (ctypes.c_double * (16 * self.count))()
+        st = lib().lbm13_batch_diagnostics(self._h, out)
+        if check:
+            self._check(st)
+        vals = np.array(list(out)).reshape(self.count, 16)
+        return [dict(zip(DIAG_NAMES, row[:len(DIAG_NAMES)])) for row in vals]
+
+    def get_state(self, i: int):
+        torch = _torch()
+        nx, ny = self.sizes[i]
+        out = torch.empty((13, ny, nx), dtype=torch.float64, device="cuda")
+        self._check(lib().lbm13_batch_get_state(self._h, int(i), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def set_state(self, i: int, src):
+        torch = _torch()
+        nx, ny = self.sizes[i]
+        t = _dev_f64(src, torch, 13 * nx * ny)
+        self._keep[("state", i)] = t
+        self._check(lib().lbm13_batch_set_state(self._h, int(i), ctypes.c_void_p(t.data_ptr())))
+
+    def set_tile(self, tile_x: int, tile_y: int):
+        self._check(lib().lbm13_batch_set_tile(self._h, int(tile_x), int(tile_y)))
+
+    def autotune(self, steps: int = 20):
+        tx, ty = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().lbm13_batch_autotune(self._h, int(steps), ctypes.byref(tx), ctypes.byref(ty)))
+        return tx.value, ty.value
+
+    def use_graph(self, k: int):
+        self._check(lib().lbm13_batch_use_graph(self._h, int(k)))
+
+    def nodes(self) -> int:
+        return int(lib().lbm13_batch_nodes(self._h))
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib().lbm13_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,353 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Both sides start from the same seeded macroscopic fields and build their own
+populations.  The library keeps the post-collision state f*(t); the oracle's
+f*(t) is collide(f(t)).
+
+Bars:
+  * FP64: max |f*_gpu - f*_oracle| <= 1e-12 max |f*_oracle| (populations),
+    rho and T within 1e-12 of the oracle relative to their maxima, u within
+    1e-12 (lattice units, cs = 1).
+  * FP32 deviation form: rho, u, T within 1e-5 of the FP64 oracle.
+  * Streaming only (collide = 0, bounce-back / periodic): bit-exact.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_0188_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _lb():
+    from paper_1401_0188_amd import lbm13
+    return lbm13
+
+
+def say(msg):
+    print("[case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def params_pair(**kw):
+    """Same parameters in the oracle's and the library's spelling."""
+    F0 = kw.pop("F0", (0.0, 0.0))
+    g = kw.pop("g", (0.0, 0.0))
+    po = oracle.params(F0x=F0[0], F0y=F0[1], gx=g[0], gy=g[1], **kw)
+    pl = dict(kw, F0=F0, g=g)
+    return po, pl
+
+
+def run_both(nx, ny, fields, steps, kinds=(0, 0, 0, 0), u_t=(0, 0, 0, 0), T_w=(0, 0, 0, 0),
+             precision=0, tile=None, **kw):
+    lbm13 = _lb()
+    po, pl = params_pair(**kw)
+    so = oracle.sides(kinds, u_t, T_w)
+    lat = lbm13.Lattice(nx, ny, precision)
+    if tile:
+        lat.set_tile(*tile)
+    lat.set_params(sides=lbm13.make_sides(kinds, u_t, T_w), **pl)
+    lat.init_moments(*fields)
+    lat.step(steps)
+    gs = lat.get_state().cpu().numpy()
+    gm = [t.cpu().numpy() for t in lat.moments()]
+    f = oracle.run(oracle.init(*fields, po), po, so, steps)
+    fs = oracle.collide(f, po)
+    om = oracle.moments(f, po)
+    return lat, gs, gm, fs, om, f, po, so
+
+
+def assert_fp64(gs, gm, fs, om, tol=1e-12):
+    err = np.abs(gs - fs).max() / np.abs(fs).max()
+    assert err <= tol, "population rel err %g" % err
+    rho_e = np.abs(gm[0] - om[0]).max() / np.abs(om[0]).max()
+    u_e = max(np.abs(gm[1] - om[1]).max(), np.abs(gm[2] - om[2]).max())
+    T_e = np.abs(gm[3] - om[3]).max() / np.abs(om[3]).max()
+    assert rho_e <= tol and u_e <= tol and T_e <= tol, (rho_e, u_e, T_e)
+
+
+def assert_fp32(gm, om, tol=1e-5):
+    errs = [np.abs(gm[k] - om[k]).max() for k in range(4)]
+    assert max(errs) <= tol, errs
+    return errs
+
+
+# --------------------------------------------------------------------------- FP64 periodic
+
+def test_fp64_periodic_wave_1000_steps():
+    say("fp64 periodic wave 32x32, 1000 steps")
+    lat, gs, gm, fs, om, *_ = run_both(32, 32, workloads.periodic_wave(32), 1000)
+    assert_fp64(gs, gm, fs, om)
+
+
+@pytest.mark.parametrize("tile", [(64, 4), (64, 8), (64, 16), (32, 8), (32, 16)])
+def test_fp64_ragged_periodic_all_tiles(tile):
+    say("fp64 periodic 97x53 tile %s" % (tile,))
+    fields = workloads.shear_acoustic(97, 53)
+    lat, gs, gm, fs, om, *_ = run_both(97, 53, fields, 60, tile=tile, F0=(1e-5, -2e-5), g=(0.0, -1e-3))
+    assert_fp64(gs, gm, fs, om)
+
+
+# --------------------------------------------------------------------------- FP64 walls
+
+WALL_CASES = {
+    # name: (nx, ny, kinds, u_t, T_w, extra params, steps)
+    "cavity": (48, 40, (2, 2, 1, 1), (0, 0, 0, 0), (-2 + 0.005, -2 - 0.005, 0, 0), dict(g=(0.0, -0.05)), 300),
+    "couette": (23, 70, (2, 2, 0, 0), (0.03, -0.01, 0, 0), (-2 + 0.01, -2 - 0.01, 0, 0), dict(), 300),
+    "poiseuille": (40, 9, (2, 2, 0, 0), (0, 0, 0, 0), (-2.0, -2.0, 0, 0), dict(F0=(0.0, 1e-5)), 300),
+    "closed_moving_adiabatic": (66, 67, (1, 1, 1, 1), (0.02, -0.01, 0.015, -0.03), (0, 0, 0, 0), dict(), 200),
+    "tiny_2x2": (2, 2, (2, 2, 1, 1), (0.01, 0, 0, 0), (-1.99, -2.01, 0, 0), dict(), 50),
+    "y_walls_x_periodic": (37, 24, (0, 0, 2, 2), (0, 0, 0.02, 0), (0, 0, -1.99, -2.01), dict(g=(0.01, 0.0)), 200),
+    "mixed_T_and_adiabatic": (70, 5, (2, 2, 1, 1), (0.01, 0.0, -0.01, 0.02), (-1.995, -2.0, 0, 0), dict(), 150),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WALL_CASES))
+def test_fp64_walls(name):
+    nx, ny, kinds, u_t, T_w, extra, steps = WALL_CASES[name]
+    say("fp64 walls %s %dx%d %d steps" % (name, nx, ny, steps))
+    fields = workloads.cavity_fields(nx, ny=ny, seed=7, dT=0.01)
+    lat, gs, gm, fs, om, *_ = run_both(nx, ny, fields, steps, kinds, u_t, T_w, **extra)
+    assert_fp64(gs, gm, fs, om)
+
+
+@pytest.mark.parametrize("tile", [(64, 4), (32, 16)])
+def test_fp64_cavity_other_tiles(tile):
+    nx, ny, kinds, u_t, T_w, extra, steps = WALL_CASES["cavity"]
+    say("fp64 cavity tile %s" % (tile,))
+    fields = workloads.cavity_fields(nx, ny=ny, seed=8)
+    lat, gs, gm, fs, om, *_ = run_both(nx, ny, fields, 120, kinds, u_t, T_w, tile=tile, **extra)
+    assert_fp64(gs, gm, fs, om)
+
+
+# --------------------------------------------------------------------------- streaming only
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("shape,kinds", [((70, 35), (1, 1, 1, 1)), ((33, 17), (0, 0, 0, 0)),
+                                         ((40, 6), (0, 0, 1, 1))])
+def test_streaming_only_is_bit_exact(precision, shape, kinds):
+    lbm13 = _lb()
+    nx, ny = shape
+    say("collide-off %s kinds %s precision %d" % (shape, kinds, precision))
+    rng = np.random.default_rng(nx * ny)
+    fields = (1 + 0.01 * rng.standard_normal((ny, nx)), 0.01 * rng.standard_normal((ny, nx)),
+              0.01 * rng.standard_normal((ny, nx)), -2 + 0.01 * rng.standard_normal((ny, nx)))
+    lat = lbm13.Lattice(nx, ny, precision)
+    lat.set_params(sides=lbm13.make_sides(kinds), collide=0)
+    lat.init_moments(*fields)
+    s0 = lat.get_state().cpu().numpy()
+    lat.step(25)
+    s1 = lat.get_state().cpu().numpy()
+    po = oracle.params(collide=0)
+    ref = oracle.run(s0, po, oracle.sides(kinds), 25)
+    assert np.array_equal(s1, ref)
+
+
+# --------------------------------------------------------------------------- FP32 deviation form
+
+@pytest.mark.timeout(900)
+def test_fp32_cavity_256_1e4_steps():
+    """Cavity of 256^2 at Ra = 1e5, Pr = 0.71 (sec. 10 geometry), 10^4 steps."""
+    lbm13 = _lb()
+    n, dT, Ra, Pr = 256, 0.01, 1e5, 0.71
+    st, d = oracle.derive(oracle.params(Pr=Pr))
+    gy = -28.0 * Ra * d["nu"] * d["kappa"] / (dT * n ** 3)
+    say("fp32 cavity 256^2 Ra=1e5 10^4 steps (g=%g)" % gy)
+    fields = workloads.cavity_fields(n, seed=0, dT=dT)
+    T_w = (-2 + dT / 2, -2 - dT / 2, 0, 0)
+    lat, gs, gm, fs, om, f, po, so = run_both(n, n, fields, 10000, (2, 2, 1, 1), (0, 0, 0, 0), T_w,
+                                              precision=lbm13.FP32_DEV, Pr=Pr, g=(0.0, gy))
+    errs = assert_fp32(gm, om)
+    say("fp32 cavity errors rho %.2e ux %.2e uy %.2e T %.2e, u_max %.3e" % (*errs, np.abs(om[2]).max()))
+    od = oracle.diagnostics(f, po, so)
+    gd = lat.diagnostics()
+    assert gd["Nu_mean"] == pytest.approx(od["Nu_mean"], rel=1e-4)
+
+
+def test_fp32_shear_wave_matches_oracle():
+    lbm13 = _lb()
+    say("fp32 shear+acoustic 256x256, 2000 steps")
+    lat, gs, gm, fs, om, *_ = run_both(256, 256, workloads.shear_acoustic(256), 2000, precision=lbm13.FP32_DEV)
+    assert_fp32(gm, om)
+
+
+# --------------------------------------------------------------------------- full size 4096^2
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_4096_matches_oracle(precision):
+    """The 4096^2 periodic shear + acoustic wave at full size, a few steps, in
+    the tile shape the benchmark uses."""
+    lbm13 = _lb()
+    from bench import BENCH_TILE
+    say("full size 4096^2 precision %d, 3 steps, tile %s" % (precision, BENCH_TILE))
+    lat, gs, gm, fs, om, *_ = run_both(4096, 4096, workloads.shear_acoustic(4096), 3, precision=precision,
+                                       tile=BENCH_TILE)
+    if precision == 0:
+        assert_fp64(gs, gm, fs, om)
+    else:
+        assert_fp32(gm, om, tol=1e-6)
+
+
+# --------------------------------------------------------------------------- diagnostics
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_diagnostics_match_oracle(precision):
+    nx, ny, kinds, u_t, T_w, extra, steps = WALL_CASES["cavity"]
+    say("diagnostics cavity precision %d" % precision)
+    fields = workloads.cavity_fields(nx, ny=ny, seed=9)
+    lat, gs, gm, fs, om, f, po, so = run_both(nx, ny, fields, 400, kinds, u_t, T_w, precision=precision, **extra)
+    gd = lat.diagnostics()
+    od = oracle.diagnostics(f, po, so)
+    tol = 1e-11 if precision == 0 else 1e-6
+    N = nx * ny
+    for k in ("sum_rho", "sum_E"):
+        assert abs(gd[k] - od[k]) <= tol * abs(od[k]), k
+    for k in ("sum_jx", "sum_jy"):
+        assert abs(gd[k] - od[k]) <= tol * N, k
+    assert gd["Nu_mean"] == pytest.approx(od["Nu_mean"], rel=1e-9 if precision == 0 else 1e-4)
+    assert gd["u_max"] == pytest.approx(od["u_max"], rel=1e-9 if precision == 0 else 1e-4)
+    assert gd["asym_abs"] == pytest.approx(od["asym_abs"], rel=1e-8 if precision == 0 else 1e-2, abs=1e-10)
+    assert gd["rho_min"] == pytest.approx(od["rho_min"], rel=1e-12 if precision == 0 else 1e-6)
+    assert gd["nonfinite"] == 0
+
+
+def test_conduction_nusselt_is_one_on_gpu():
+    lbm13 = _lb()
+    W, ny, dT = 16, 4, 0.01
+    say("conduction Nu on GPU")
+    lat = lbm13.Lattice(W, ny, lbm13.FP64)
+    d = lat.set_params(sides=lbm13.make_sides((2, 2, 0, 0), (0, 0, 0, 0), (-2 + dT / 2, -2 - dT / 2, 0, 0)))
+    lat.init_moments(*workloads.rest_fields(W, ny))
+    lat.step(int(8 * W * W / d["kappa"]))
+    assert lat.diagnostics()["Nu_mean"] == pytest.approx(1.0, abs=2e-3)
+
+
+# --------------------------------------------------------------------------- batched form
+
+def test_batch_matches_oracle_per_domain():
+    lbm13 = _lb()
+    cases = [
+        (48, 40, (2, 2, 1, 1), (0, 0, 0, 0), (-1.995, -2.005, 0, 0), dict(g=(0.0, -0.05), Pr=0.71, s_XX=1.6)),
+        (23, 70, (2, 2, 0, 0), (0.03, 0, 0, 0), (-1.99, -2.01, 0, 0), dict(s_XX=1.2, Pr=1.0)),
+        (97, 53, (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0), dict(F0=(1e-5, 0.0))),
+        (40, 9, (2, 2, 0, 0), (0, 0, 0, 0), (-2.0, -2.0, 0, 0), dict(F0=(0.0, 1e-5), s_XX=1.4)),
+        (130, 66, (1, 1, 1, 1), (0.01, 0, 0, -0.02), (0, 0, 0, 0), dict()),
+    ]
+    for precision in (0, 1):
+        say("batch of %d domains precision %d" % (len(cases), precision))
+        b = lbm13.Batch([(c[0], c[1]) for c in cases], precision)
+        fields = []
+        for i, (nx, ny, kinds, u_t, T_w, kw) in enumerate(cases):
+            po, pl = params_pair(**dict(kw))
+            b.set_params(i, sides=lbm13.make_sides(kinds, u_t, T_w), **pl)
+            fields.append(workloads.cavity_fields(nx, ny=ny, seed=20 + i))
+            b.init_moments(i, *fields[-1])
+        b.use_graph(10)
+        b.step(150)
+        for i, (nx, ny, kinds, u_t, T_w, kw) in enumerate(cases):
+            po, pl = params_pair(**dict(kw))
+            so = oracle.sides(kinds, u_t, T_w)
+            f = oracle.run(oracle.init(*fields[i], po), po, so, 150)
+            gm = [t.cpu().numpy() for t in b.moments(i)]
+            om = oracle.moments(f, po)
+            if precision == 0:
+                assert_fp64(b.get_state(i).cpu().numpy(), gm, oracle.collide(f, po), om)
+            else:
+                assert_fp32(gm, om)
+
+
+# --------------------------------------------------------------------------- runtime
+
+def test_graph_replay_is_bit_exact_with_direct_steps():
+    lbm13 = _lb()
+    import torch
+    say("graph replay vs direct launches")
+    fields = workloads.cavity_fields(128, ny=96, seed=3)
+    sides = lbm13.make_sides((2, 2, 1, 1), (0, 0, 0, 0), (-1.995, -2.005, 0, 0))
+    a = lbm13.Lattice(128, 96, lbm13.FP32_DEV)
+    a.set_params(sides=sides, g=(0.0, -0.05))
+    a.init_moments(*fields)
+    a.step(40)
+    ref = a.get_state().cpu().numpy()
+    b = lbm13.Lattice(128, 96, lbm13.FP32_DEV)
+    b.set_params(sides=sides, g=(0.0, -0.05))
+    b.init_moments(*fields)
+    b.use_graph(8)
+    for _ in range(5):
+        b.step(8)
+        torch.cuda.synchronize()
+        _ = [t.sum().item() for t in b.moments()]  # eager work between replays
+    assert b.steps_done() == 40
+    assert np.array_equal(b.get_state().cpu().numpy(), ref)
+    b.step(3)  # odd remainder through direct launches, then graphs of the other parity
+    b.step(16)
+    a.step(19)
+    assert np.array_equal(b.get_state().cpu().numpy(), a.get_state().cpu().numpy())
+
+
+def test_checkpoint_resume_is_bit_exact():
+    lbm13 = _lb()
+    say("checkpoint / resume")
+    fields = workloads.periodic_wave(64)
+    lat = lbm13.Lattice(64, 64, lbm13.FP64)
+    lat.set_params()
+    lat.init_moments(*fields)
+    lat.step(30)
+    saved = lat.get_state().clone()
+    lat.step(30)
+    s1 = lat.get_state().cpu().numpy()
+    lat.set_state(saved)
+    lat.step(30)
+    assert np.array_equal(lat.get_state().cpu().numpy(), s1)
+
+
+def test_error_paths():
+    lbm13 = _lb()
+    say("error paths")
+    lat = lbm13.Lattice(32, 32, lbm13.FP64)
+    with pytest.raises(lbm13.LBM13Error) as e:
+        lat.step(1)
+    assert e.value.code == lbm13.ESTATE
+    with pytest.raises(lbm13.LBM13Error) as e:
+        lat.set_tile(48, 4)
+    assert e.value.code == lbm13.EINVAL
+    with pytest.raises(lbm13.LBM13Error) as e:
+        lat.set_params(s_XX=2.5)
+    assert e.value.code == lbm13.EUNSTABLE_PARAMS
+    with pytest.raises(lbm13.LBM13Error) as e:
+        lat.set_params(sides=lbm13.make_sides((0, 1, 0, 0)))
+    assert e.value.code == lbm13.EINVAL
+    with pytest.raises(lbm13.LBM13Error) as e:
+        lat.use_graph(3)
+    assert e.value.code == lbm13.EINVAL
+    lat.set_params()
+    lat.init_moments(*workloads.periodic_wave(32))
+    st = lat.get_state()
+    st[3, 5, 7] = float("nan")
+    lat.set_state(st)
+    with pytest.raises(lbm13.LBM13Error) as e:
+        lat.diagnostics()
+    assert e.value.code == lbm13.ENONFINITE
+    assert lat.diagnostics(check=False)["nonfinite"] == 1
+
+
+def test_autotune_keeps_results():
+    lbm13 = _lb()
+    say("autotune")
+    fields = workloads.cavity_fields(200, ny=150, seed=4)
+    sides = lbm13.make_sides((2, 2, 1, 1), (0, 0, 0, 0), (-1.995, -2.005, 0, 0))
+    lat = lbm13.Lattice(200, 150, lbm13.FP64)
+    lat.set_params(sides=sides)
+    lat.init_moments(*fields)
+    tx, ty = lat.autotune(4)
+    assert (tx, ty) in lbm13.TILE_SHAPES
+    n = lat.steps_done()
+    po = oracle.params()
+    f = oracle.run(oracle.init(*fields, po), po, oracle.sides((2, 2, 1, 1), (0, 0, 0, 0), (-1.995, -2.005, 0, 0)), n)
+    assert_fp64(lat.get_state().cpu().numpy(), [t.cpu().numpy() for t in lat.moments()], oracle.collide(f, po),
+                oracle.moments(f, po))
