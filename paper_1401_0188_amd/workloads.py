@@ -85,3 +85,26 @@ def channel_batch(count: int = 128, seed: int = 5, len_lo: int = 256, len_hi: in
 
 def rest_fields(nx: int, ny: int, T0: float = -2.0):
     return (np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)), np.full((ny, nx), T0))
+
+
+def cavity_forcing(L: int, Ra: float, Pr: float, nu: float, kappa: float, eps_h: float = 0.2,
+                   dT_min: float = 0.01, dT_max: float = 1.0, mach_max: float = 0.1, cs: float = 1.0):
+    """Temperature difference and gravity for a heated cavity of side L at Rayleigh
+    number Ra (eq intro-rayleigh with beta = 1/28: an isobaric change dE of the
+    D2Q13 energy changes rho by -dE/28).
+
+    |g| = 28 Ra nu kappa / (dT L^3).  Two limits make the run meaningful: the
+    hydrostatic parameter |g| L / cs^2 (density scale height over cavity size)
+    stays <= eps_h, and the free-fall Mach number sqrt(Ra/Pr) nu / (L cs) stays
+    <= mach_max.  dT is the smallest value in [dT_min, dT_max] meeting the
+    first; when no dT does, or the Mach limit is broken, Ra is lowered to the
+    largest feasible value and `clamped` is set.  Inputs nu, kappa come from the
+    caller's own parameter derivation."""
+    Ra_eff = float(Ra)
+    ra_mach = Pr * (mach_max * L * cs / nu) ** 2
+    ra_hydro = eps_h * cs * cs * dT_max * L * L / (28.0 * nu * kappa)
+    Ra_eff = min(Ra_eff, ra_mach, ra_hydro)
+    dT = min(dT_max, max(dT_min, 28.0 * Ra_eff * nu * kappa / (eps_h * cs * cs * L * L)))
+    g = 28.0 * Ra_eff * nu * kappa / (dT * L ** 3)
+    return dict(dT=dT, g=g, Ra=Ra_eff, Ra_requested=float(Ra), clamped=Ra_eff < Ra,
+                hydro=g * L / (cs * cs), mach=(Ra_eff / Pr) ** 0.5 * nu / (L * cs))
