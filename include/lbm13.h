@@ -156,7 +156,16 @@ int lbm13_diagnostics(lbm13_ctx *ctx, double out[16]);
 int lbm13_get_state(lbm13_ctx *ctx, double *dst);
 int lbm13_set_state(lbm13_ctx *ctx, const double *src);
 
-/* Number of steps taken since the last init/set_state... (init resets it). */
+/* Raw checkpoint of the kept state: 13*ny*nx values of the storage precision
+ * (8 bytes for LBM13_FP64, 4 for LBM13_FP32_DEV), the stored deviations from
+ * the rest populations, dense [13][ny][nx], in the device buffer dst of
+ * lbm13_state_bytes() bytes.  lbm13_load() restores it bit-exactly, so a run
+ * resumed from a checkpoint equals the uninterrupted run.  Async. */
+size_t lbm13_state_bytes(const lbm13_ctx *ctx);
+int lbm13_save(lbm13_ctx *ctx, void *dst);
+int lbm13_load(lbm13_ctx *ctx, const void *src);
+
+/* Number of steps taken since the last lbm13_init_moments() (which resets it). */
 long long lbm13_steps_done(const lbm13_ctx *ctx);
 
 /* Tile shape of the step kernel: tile_x in {32, 64} nodes along x, tile_y in
@@ -200,6 +209,9 @@ int lbm13_batch_moments(lbm13_batch *b, int i, double *rho, double *ux, double *
 int lbm13_batch_diagnostics(lbm13_batch *b, double *out);
 int lbm13_batch_get_state(lbm13_batch *b, int i, double *dst);
 int lbm13_batch_set_state(lbm13_batch *b, int i, const double *src);
+size_t lbm13_batch_state_bytes(const lbm13_batch *b, int i);
+int lbm13_batch_save(lbm13_batch *b, int i, void *dst);
+int lbm13_batch_load(lbm13_batch *b, int i, const void *src);
 int lbm13_batch_set_tile(lbm13_batch *b, int tile_x, int tile_y);
 int lbm13_batch_autotune(lbm13_batch *b, int steps, int *tile_x, int *tile_y);
 int lbm13_batch_use_graph(lbm13_batch *b, int k);

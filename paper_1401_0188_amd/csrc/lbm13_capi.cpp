@@ -611,6 +611,44 @@ int lbm13_batch_set_state(lbm13_batch* b, int i, const double* src) {
     return LBM13_OK;
 }
 
+size_t lbm13_batch_state_bytes(const lbm13_batch* b, int i) {
+    if (!b || i < 0 || i >= b->count) return 0;
+    return (size_t)13 * b->nx[i] * b->ny[i] * (b->precision == LBM13_FP64 ? 8 : 4);
+}
+
+// Raw copies between the padded planes and a dense [13][ny][nx] array.
+static int raw_copy(lbm13_batch* b, int i, void* dense, const void* dense_src) {
+    const size_t es = b->precision == LBM13_FP64 ? 8 : 4;
+    char* plane0 = b->ws + (b->cur ? b->L.bufB : b->L.bufA) + es * (size_t)b->L.off[i];
+    const size_t row = es * b->nx[i], pitch = es * b->L.pitch[i], plane = es * (size_t)b->L.plane[i];
+    const size_t dplane = row * b->ny[i];
+    for (int q = 0; q < 13; ++q) {
+        hipError_t e;
+        if (dense)
+            e = hipMemcpy2DAsync(static_cast<char*>(dense) + q * dplane, row, plane0 + q * plane, pitch, row,
+                                 b->ny[i], hipMemcpyDeviceToDevice, b->stream);
+        else
+            e = hipMemcpy2DAsync(plane0 + q * plane, pitch, static_cast<const char*>(dense_src) + q * dplane, row,
+                                 row, b->ny[i], hipMemcpyDeviceToDevice, b->stream);
+        if (e != hipSuccess) return hip_fail(b, e, "raw state copy");
+    }
+    return LBM13_OK;
+}
+
+int lbm13_batch_save(lbm13_batch* b, int i, void* dst) {
+    if (!check_index(b, i) || !dst) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    if (!b->has_state[i]) return fail(b, LBM13_ESTATE, "no state");
+    return raw_copy(b, i, dst, nullptr);
+}
+
+int lbm13_batch_load(lbm13_batch* b, int i, const void* src) {
+    if (!check_index(b, i) || !src) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    if (!b->has_params[i]) return fail(b, LBM13_ESTATE, "set_params first");
+    int st = raw_copy(b, i, nullptr, src);
+    if (st == LBM13_OK) b->has_state[i] = 1;
+    return st;
+}
+
 int lbm13_batch_set_tile(lbm13_batch* b, int tile_x, int tile_y) {
     if (!b) return LBM13_EINVAL;
     if (!valid_shape(tile_x, tile_y)) return fail(b, LBM13_EINVAL, "unsupported tile shape");
@@ -696,6 +734,12 @@ int lbm13_set_state(lbm13_ctx* c, const double* src) {
 }
 
 long long lbm13_steps_done(const lbm13_ctx* c) { return c && c->b ? c->b->steps : 0; }
+
+size_t lbm13_state_bytes(const lbm13_ctx* c) { return c ? lbm13_batch_state_bytes(c->b, 0) : 0; }
+
+int lbm13_save(lbm13_ctx* c, void* dst) { return c ? lbm13_batch_save(c->b, 0, dst) : LBM13_EINVAL; }
+
+int lbm13_load(lbm13_ctx* c, const void* src) { return c ? lbm13_batch_load(c->b, 0, src) : LBM13_EINVAL; }
 
 int lbm13_set_tile(lbm13_ctx* c, int tile_x, int tile_y) {
     return c ? lbm13_batch_set_tile(c->b, tile_x, tile_y) : LBM13_EINVAL;

@@ -87,6 +87,9 @@ def lib():
         "lbm13_get_state": (i32, [vp, dp]),
         "lbm13_set_state": (i32, [vp, dp]),
         "lbm13_steps_done": (i64, [vp]),
+        "lbm13_state_bytes": (sz, [vp]),
+        "lbm13_save": (i32, [vp, vp]),
+        "lbm13_load": (i32, [vp, vp]),
         "lbm13_set_tile": (i32, [vp, i32, i32]),
         "lbm13_autotune": (i32, [vp, i32, ip, ip]),
         "lbm13_use_graph": (i32, [vp, i32]),
@@ -101,6 +104,9 @@ def lib():
         "lbm13_batch_diagnostics": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
         "lbm13_batch_get_state": (i32, [vp, i32, dp]),
         "lbm13_batch_set_state": (i32, [vp, i32, dp]),
+        "lbm13_batch_state_bytes": (sz, [vp, i32]),
+        "lbm13_batch_save": (i32, [vp, i32, vp]),
+        "lbm13_batch_load": (i32, [vp, i32, vp]),
         "lbm13_batch_set_tile": (i32, [vp, i32, i32]),
         "lbm13_batch_autotune": (i32, [vp, i32, ip, ip]),
         "lbm13_batch_use_graph": (i32, [vp, i32]),
@@ -239,6 +245,17 @@ class Lattice(_Base):
         self._keep = [t]
         self._check(lib().lbm13_set_state(self._h, ctypes.c_void_p(t.data_ptr())))
 
+    def save(self):
+        """Raw checkpoint (device uint8 tensor) of the stored working-precision state."""
+        torch = _torch()
+        out = torch.empty(int(lib().lbm13_state_bytes(self._h)), dtype=torch.uint8, device="cuda")
+        self._check(lib().lbm13_save(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def load(self, blob):
+        self._keep = [blob]
+        self._check(lib().lbm13_load(self._h, ctypes.c_void_p(blob.data_ptr())))
+
     def steps_done(self) -> int:
         return int(lib().lbm13_steps_done(self._h))
 
@@ -337,6 +354,16 @@ class Batch(_Base):
         t = _dev_f64(src, torch, 13 * nx * ny)
         self._keep[("state", i)] = t
         self._check(lib().lbm13_batch_set_state(self._h, int(i), ctypes.c_void_p(t.data_ptr())))
+
+    def save(self, i: int):
+        torch = _torch()
+        out = torch.empty(int(lib().lbm13_batch_state_bytes(self._h, int(i))), dtype=torch.uint8, device="cuda")
+        self._check(lib().lbm13_batch_save(self._h, int(i), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def load(self, i: int, blob):
+        self._keep[("blob", i)] = blob
+        self._check(lib().lbm13_batch_load(self._h, int(i), ctypes.c_void_p(blob.data_ptr())))
 
     def set_tile(self, tile_x: int, tile_y: int):
         self._check(lib().lbm13_batch_set_tile(self._h, int(tile_x), int(tile_y)))

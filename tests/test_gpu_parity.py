@@ -294,20 +294,28 @@ def test_graph_replay_is_bit_exact_with_direct_steps():
     assert np.array_equal(b.get_state().cpu().numpy(), a.get_state().cpu().numpy())
 
 
-def test_checkpoint_resume_is_bit_exact():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_checkpoint_resume_is_bit_exact(precision):
     lbm13 = _lb()
-    say("checkpoint / resume")
-    fields = workloads.periodic_wave(64)
-    lat = lbm13.Lattice(64, 64, lbm13.FP64)
-    lat.set_params()
+    say("checkpoint / resume precision %d" % precision)
+    fields = workloads.cavity_fields(64, ny=48, seed=12)
+    sides = lbm13.make_sides((2, 2, 1, 1), (0.01, 0, 0, 0), (-1.995, -2.005, 0, 0))
+    lat = lbm13.Lattice(64, 48, precision)
+    lat.set_params(sides=sides, g=(0.0, -0.01))
     lat.init_moments(*fields)
     lat.step(30)
-    saved = lat.get_state().clone()
+    blob = lat.save()
+    absolute = lat.get_state()
     lat.step(30)
     s1 = lat.get_state().cpu().numpy()
-    lat.set_state(saved)
+    lat.load(blob)
     lat.step(30)
     assert np.array_equal(lat.get_state().cpu().numpy(), s1)
+    # the absolute FP64 view round-trips within the rounding of one subtraction
+    lat.set_state(absolute)
+    back = lat.get_state()
+    tol = 1e-16 if precision == 0 else 1e-8
+    assert float((back - absolute).abs().max()) <= tol
 
 
 def test_error_paths():
