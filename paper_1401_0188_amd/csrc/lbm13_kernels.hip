@@ -519,38 +519,55 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(const R* __restrict__
     }
 }
 
-// Pass 2: one thread per domain walks its partial records in order.
+// Pass 2: one 256-thread block per domain.  Thread k combines records
+// k, k + 256, ... in that order, then a fixed-shape tree in LDS combines the
+// threads, so the result is independent of scheduling.
 template <typename R>
-__global__ void diag_final_kernel(const Dom<R>* __restrict__ doms, int ndom, const double* __restrict__ part,
-                                  double* __restrict__ out) {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= ndom) return;
+__global__ __launch_bounds__(256) void diag_final_kernel(const Dom<R>* __restrict__ doms,
+                                                         const double* __restrict__ part,
+                                                         double* __restrict__ out) {
+    const int d = blockIdx.x;
     const Dom<R>& D = doms[d];
-    double s[5] = {0, 0, 0, 0, 0};
-    double umax = 0.0, asym = 0.0, nonfin = 0.0, rmin = INFINITY;
-    for (int t = D.tile0; t < D.tile0 + D.ntiles; ++t) {
+    const int k = threadIdx.x;
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, INFINITY};
+    for (int t = D.tile0 + k; t < D.tile0 + D.ntiles; t += 256) {
         const double* p = part + t * kDiagPartials;
-        for (int k = 0; k < 5; ++k) s[k] += p[k];
-        umax = fmax(umax, p[5]);
-        asym = fmax(asym, p[6]);
-        nonfin += p[7];
-        rmin = fmin(rmin, p[8]);
+        for (int j = 0; j < 5; ++j) v[j] += p[j];
+        v[5] = fmax(v[5], p[5]);
+        v[6] = fmax(v[6], p[6]);
+        v[7] += p[7];
+        v[8] = fmin(v[8], p[8]);
     }
+    __shared__ double red[9][256];
+    for (int j = 0; j < 9; ++j) red[j][k] = v[j];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (k < h) {
+            for (int j = 0; j < 5; ++j) red[j][k] += red[j][k + h];
+            red[5][k] = fmax(red[5][k], red[5][k + h]);
+            red[6][k] = fmax(red[6][k], red[6][k + h]);
+            red[7][k] += red[7][k + h];
+            red[8][k] = fmin(red[8][k], red[8][k + h]);
+        }
+        __syncthreads();
+    }
+    if (k != 0) return;
     const double N = double(D.nx) * double(D.ny);
     const int faces = D.xper ? D.nx : D.nx - 3;
     double* o = out + d * kDiagOut;
-    o[0] = N + s[0];
-    o[1] = s[1];
-    o[2] = s[2];
-    o[3] = N * D.E0 + s[3];
-    o[4] = s[4];
-    o[5] = (faces > 0) ? s[4] / (double(faces) * D.ny) * D.nu_scale : 0.0;
+    const double umax = red[5][0];
+    o[0] = N + red[0][0];
+    o[1] = red[1][0];
+    o[2] = red[2][0];
+    o[3] = N * D.E0 + red[3][0];
+    o[4] = red[4][0];
+    o[5] = (faces > 0) ? red[4][0] / (double(faces) * D.ny) * D.nu_scale : 0.0;
     o[6] = umax;
-    o[7] = asym;
-    o[8] = umax > 0.0 ? asym / umax : 0.0;
-    o[9] = nonfin;
-    o[10] = rmin;
-    for (int k = 11; k < kDiagOut; ++k) o[k] = 0.0;
+    o[7] = red[6][0];
+    o[8] = umax > 0.0 ? red[6][0] / umax : 0.0;
+    o[9] = red[7][0];
+    o[10] = red[8][0];
+    for (int j = 11; j < kDiagOut; ++j) o[j] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -591,7 +608,7 @@ hipError_t launch_diag(int tile_x, int tile_y, const R* src, const Dom<R>* doms,
             else diag_partial_kernel<R, 32, 2><<<nall, blk, 0, s>>>(src, doms, all, part);
         }
     }
-    diag_final_kernel<R><<<(ndom + 63) / 64, 64, 0, s>>>(doms, ndom, part, out);
+    diag_final_kernel<R><<<ndom, 256, 0, s>>>(doms, part, out);
     return hipGetLastError();
 }
 
