@@ -98,6 +98,130 @@ def run_form(precision, n, steps, warmup, diag_every, tile, graph_k):
                 mass_drift=drift, nodes=nodes)
 
 
+def cavity_specs(count=64, seed=4):
+    """Heated cavities of uneven sizes (side U{64..512}), Ra log-uniform in
+    [1e3, 1e6], Pr U[0.5, 7] (one seeded draw per cavity), each with its own
+    parameter set and feasible forcing (Ra clamped and recorded when needed)."""
+    from paper_1401_0188_amd import lbm13, workloads
+    out = []
+    for i, c in enumerate(workloads.cavity_batch(count=count, seed=seed)):
+        kw = workloads.cavity_parameter_set(c["Pr"])
+        st, d = lbm13.derive(**kw)
+        cf = workloads.cavity_forcing(c["nx"], c["Ra"], c["Pr"], d["nu"], d["kappa"])
+        E0 = kw["E0"]
+        out.append(dict(nx=c["nx"], ny=c["ny"], kw=dict(kw, g=(0.0, -cf["g"])),
+                        sides=((2, 2, 1, 1), (0, 0, 0, 0), (E0 + cf["dT"] / 2, E0 - cf["dT"] / 2, 0, 0)),
+                        fields=("cavity", dict(n=c["nx"], T0=E0, dT=cf["dT"], seed=seed * 1000 + i)),
+                        info=dict(Pr=c["Pr"], Ra=c["Ra"], Ra_eff=cf["Ra"], clamped=cf["clamped"])))
+    return out
+
+
+def channel_specs(count=128, seed=5):
+    """Couette (even index) and Poiseuille (odd index) channels, periodic along
+    y, temperature walls E0 +- dT (sec. 7), viscosity from the speed limit."""
+    from paper_1401_0188_amd import workloads
+    out = []
+    E0 = -2.0
+    for c in workloads.channel_batch(count=count, seed=seed):
+        if c["kind"] == "poiseuille":
+            cv = workloads.channel_viscosity(c["nx"], c["F"])
+            kw = dict(s_XX=workloads.s_xx_for_nu(cv["nu"]), F0=(0.0, cv["F"]), E0=E0)
+            u_w = 0.0
+        else:
+            cv = dict(nu=0.0625, F=0.0, clamped=False)
+            kw = dict(s_XX=workloads.s_xx_for_nu(0.0625), E0=E0)
+            u_w = c["U"]
+        out.append(dict(nx=c["nx"], ny=c["ny"], kw=kw,
+                        sides=((2, 2, 0, 0), (u_w, 0, 0, 0), (E0 + c["dT"], E0 - c["dT"], 0, 0)),
+                        fields=("rest", dict(nx=c["nx"], ny=c["ny"], T0=E0)),
+                        info=dict(kind=c["kind"], nu=cv["nu"], clamped=cv["clamped"])))
+    return out
+
+
+def spec_fields(spec):
+    from paper_1401_0188_amd import workloads
+    kind, a = spec["fields"]
+    if kind == "cavity":
+        return workloads.cavity_fields(a["n"], T0=a["T0"], dT=a["dT"], seed=a["seed"])
+    return workloads.rest_fields(a["nx"], a["ny"], a["T0"])
+
+
+def build_batch(specs, precision):
+    from paper_1401_0188_amd import lbm13
+    b = lbm13.Batch([(s["nx"], s["ny"]) for s in specs], precision)
+    for i, s in enumerate(specs):
+        b.set_params(i, sides=lbm13.make_sides(*s["sides"]), **s["kw"])
+        b.init_moments(i, *spec_fields(s))
+    return b
+
+
+def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=True):
+    import torch
+    b = build_batch(specs, precision)
+    tile = None
+    if autotune:
+        tile = b.autotune(10)
+        b.destroy()
+        b = build_batch(specs, precision)  # fresh state after tuning
+        b.set_tile(*tile)
+    if graph_k:
+        b.use_graph(graph_k)
+    b.step(warmup)
+    b.diagnostics()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = []
+    t0 = time.perf_counter()
+    done = 0
+    chunk = diag_every if diag_every > 0 else steps
+    while done < steps:
+        k = min(chunk, steps - done)
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        b.step(k)
+        e.record(stream)
+        ev.append((a, e, k))
+        if diag_every > 0:
+            b.diagnostics()
+        done += k
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = sum(a.elapsed_time(e) for a, e, _ in ev)
+    diag = b.diagnostics()
+    nodes = b.nodes()
+    b.destroy()
+    torch.cuda.empty_cache()
+    return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=kern_ms / steps,
+                mlups=nodes * steps / wall / 1e6, nodes=nodes, tile=tile, diag=diag)
+
+
+def run_sequential_fp64(specs, steps):
+    """The same domains as separate plain FP64 contexts, stepped one after another."""
+    import torch
+    from paper_1401_0188_amd import lbm13
+    lats = []
+    for s in specs:
+        lat = lbm13.Lattice(s["nx"], s["ny"], lbm13.FP64)
+        lat.set_params(sides=lbm13.make_sides(*s["sides"]), **s["kw"])
+        lat.init_moments(*spec_fields(s))
+        lats.append(lat)
+    for lat in lats:
+        lat.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for lat in lats:
+            lat.step(1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nodes = sum(s["nx"] * s["ny"] for s in specs)
+    for lat in lats:
+        lat.destroy()
+    del lats
+    torch.cuda.empty_cache()
+    return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, mlups=nodes * steps / wall / 1e6, nodes=nodes)
+
+
 def copy_bandwidth():
     import torch
     nbytes = 2 << 30
@@ -139,21 +263,89 @@ def cpu_baseline(n, budget_s):
                 sample="%d steps of the %dx%d periodic shear + acoustic wave, FP64 oracle, %.1f s" % (steps, n, n, el))
 
 
+def roofline(nodes, kernel_ms, precision, traffic=None):
+    achieved = BYTES_PER_LU[precision] * nodes / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic}
+
+
+def cpu_baseline_spec(spec, budget_s):
+    """The FP64 oracle on one domain of a batched workload for about budget_s."""
+    import numpy as np
+
+    import oracle
+    kw = dict(spec["kw"])
+    F0 = kw.pop("F0", (0.0, 0.0))
+    g = kw.pop("g", (0.0, 0.0))
+    p = oracle.params(F0x=F0[0], F0y=F0[1], gx=g[0], gy=g[1], **kw)
+    s = oracle.sides(*spec["sides"])
+    f = oracle.init(*[np.asarray(a) for a in spec_fields(spec)], p)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        f = oracle.step(f, p, s)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    n = spec["nx"] * spec["ny"]
+    return dict(value=round(n * steps / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+                sample="%d steps of one %dx%d domain of the workload, FP64 oracle, %.1f s" % (
+                    steps, spec["nx"], spec["ny"], el))
+
+
+def main_batched(args, copy_gbps):
+    from paper_1401_0188_amd import lbm13
+    specs = cavity_specs() if args.workload == "cavities64" else channel_specs()
+    graph_k = 0 if args.no_graph else GRAPH_K
+    log("%s: %d domains, batched fp32-deviation, %d steps" % (args.workload, len(specs), args.steps))
+    r32 = run_batch(specs, lbm13.FP32_DEV, args.steps, args.warmup, args.diag_every, graph_k)
+    log("batched fp32: %.1f MLUPS, kernel %.4f ms, tile %s" % (r32["mlups"], r32["kernel_ms_per_launch"], r32["tile"]))
+    fp64_steps = args.fp64_steps if args.fp64_steps >= 0 else max(1, args.steps // 4)
+    log("sequential plain fp64: %d steps" % fp64_steps)
+    r64 = run_sequential_fp64(specs, fp64_steps)
+    log("sequential fp64: %.1f MLUPS" % r64["mlups"])
+    cpu = None
+    if not args.no_cpu:
+        big = max(range(len(specs)), key=lambda i: specs[i]["nx"] * specs[i]["ny"])
+        cpu = cpu_baseline_spec(specs[big], args.cpu_seconds)
+    clamped = sum(1 for s in specs if s["info"].get("clamped"))
+    nonfinite = sum(1 for d in r32["diag"] if d["nonfinite"] > 0)
+    return {
+        "metric": METRIC, "value": round(r32["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%s: %d domains, %d nodes" % (args.workload, len(specs), r32["nodes"]),
+                   "form": "fp32-deviation batched, one launch per step", "tile": r32["tile"],
+                   "graph_steps": graph_k, "diag_every": args.diag_every, "clamped_domains": clamped},
+        "roofline": roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1),
+        "cpu_baseline": cpu,
+        "fp64_sequential": {"value": round(r64["mlups"], 1), "unit": "MLUPS",
+                            "ms_per_step": round(r64["ms_per_step"], 5), "steps": fp64_steps,
+                            "launches_per_step": len(specs)},
+        "speedup_vs_fp64_sequential": round(r32["mlups"] / r64["mlups"], 3),
+        "kernel_ms_per_launch": round(r32["kernel_ms_per_launch"], 5),
+        "copy_GBps": round(copy_gbps, 1),
+        "domains_nonfinite": nonfinite,
+        "kernel_source_sha": kernel_sha(),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--workload", default="wave4096", choices=["wave4096", "cavities64", "channels128"])
+    ap.add_argument("--size", type=int, default=4096, help="side of the periodic wave (wave4096)")
     ap.add_argument("--diag-every", type=int, default=1000)
-    ap.add_argument("--fp64-steps", type=int, default=-1, help="steps of the plain FP64 form (default steps/2)")
+    ap.add_argument("--fp64-steps", type=int, default=-1, help="steps of the plain FP64 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the domain would shard as y-slabs with 2-row halos; see the design notes)", file=sys.stderr)
+              "(a domain would shard as y-slabs exchanging 2-row halos)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -163,10 +355,14 @@ def main():
     from paper_1401_0188_amd import lbm13
     lbm13.lib()
 
-    n = args.size
-    graph_k = 0 if args.no_graph else GRAPH_K
     log("device copy bandwidth")
     copy_gbps = copy_bandwidth()
+    if args.workload != "wave4096":
+        print(json.dumps(main_batched(args, copy_gbps)), flush=True)
+        return
+
+    n = args.size
+    graph_k = 0 if args.no_graph else GRAPH_K
     log("fp32-deviation %dx%d: %d warmup + %d steps" % (n, n, args.warmup, args.steps))
     r32 = run_form(lbm13.FP32_DEV, n, args.steps, args.warmup, args.diag_every, BENCH_TILE, graph_k)
     log("fp32: %.1f MLUPS, kernel %.4f ms" % (r32["mlups"], r32["kernel_ms_per_launch"]))
@@ -175,17 +371,13 @@ def main():
     r64 = run_form(lbm13.FP64, n, fp64_steps, max(1, args.warmup // 2), args.diag_every, BENCH_TILE, graph_k)
     log("fp64: %.1f MLUPS, kernel %.4f ms" % (r64["mlups"], r64["kernel_ms_per_launch"]))
 
-    def roof(r, prec):
-        achieved = BYTES_PER_LU[prec] * r["nodes"] / (r["kernel_ms_per_launch"] * 1e-3) / 1e9
-        t = measured_traffic(prec)
-        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": t}
-
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) for about %.0f s" % args.cpu_seconds)
         cpu = cpu_baseline(n, args.cpu_seconds)
 
+    roof32 = roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, measured_traffic(1))
+    roof64 = roofline(r64["nodes"], r64["kernel_ms_per_launch"], 0, measured_traffic(0))
     out = {
         "metric": METRIC,
         "value": round(r32["mlups"], 1),
@@ -202,15 +394,15 @@ def main():
         "config": {"workload": "periodic %dx%d transverse shear + acoustic wave" % (n, n), "nx": n, "ny": n,
                    "form": "fp32-deviation", "tile": list(BENCH_TILE), "graph_steps": graph_k,
                    "diag_every": args.diag_every},
-        "roofline": roof(r32, 1),
+        "roofline": roof32,
         "cpu_baseline": cpu,
         "fp64": {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
-                 "roofline": roof(r64, 0), "steps": fp64_steps},
+                 "roofline": roof64, "steps": fp64_steps},
         "speedup_vs_fp64": round(r32["mlups"] / r64["mlups"], 3),
         "kernel_ms_per_launch": {"fp32": round(r32["kernel_ms_per_launch"], 5),
                                  "fp64": round(r64["kernel_ms_per_launch"], 5)},
         "copy_GBps": round(copy_gbps, 1),
-        "frac_of_copy": round(roof(r32, 1)["achieved"] / copy_gbps, 4),
+        "frac_of_copy": round(roof32["achieved"] / copy_gbps, 4),
         "mass_drift": {"fp32": r32["mass_drift"], "fp64": r64["mass_drift"]},
         "kernel_source_sha": kernel_sha(),
     }

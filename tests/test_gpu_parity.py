@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
+from analytic import startup_conduction, startup_couette, startup_poiseuille
 from paper_1401_0188_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -363,3 +364,74 @@ def test_autotune_keeps_results():
     f = oracle.run(oracle.init(*fields, po), po, oracle.sides((2, 2, 1, 1), (0, 0, 0, 0), (-1.995, -2.005, 0, 0)), n)
     assert_fp64(lat.get_state().cpu().numpy(), [t.cpu().numpy() for t in lat.moments()], oracle.collide(f, po),
                 oracle.moments(f, po))
+
+
+# --------------------------------------------------------------------------- batched workloads at full size
+
+def _oracle_for_spec(spec, steps):
+    import bench
+    kw = dict(spec["kw"])
+    F0 = kw.pop("F0", (0.0, 0.0))
+    g = kw.pop("g", (0.0, 0.0))
+    po = oracle.params(F0x=F0[0], F0y=F0[1], gx=g[0], gy=g[1], **kw)
+    so = oracle.sides(*spec["sides"])
+    f = oracle.run(oracle.init(*bench.spec_fields(spec), po), po, so, steps)
+    return oracle.moments(f, po)
+
+
+@pytest.mark.parametrize("workload", ["cavities64", "channels128"])
+def test_batched_workload_full_size_sampled_parity(workload):
+    """The full batched workload (64 cavities / 128 channels of uneven sizes,
+    FP32 deviation form, graphs, the benchmark's tile) against the FP64 oracle
+    on the smallest domains, which the oracle finishes in seconds."""
+    lbm13 = _lb()
+    import bench
+    specs = bench.cavity_specs() if workload == "cavities64" else bench.channel_specs()
+    steps = 300
+    say("%s full batch, %d domains, %d steps" % (workload, len(specs), steps))
+    b = bench.build_batch(specs, lbm13.FP32_DEV)
+    b.set_tile(*bench.BENCH_TILE)
+    b.use_graph(50)
+    b.step(steps)
+    diags = b.diagnostics()
+    assert all(d["nonfinite"] == 0 for d in diags)
+    order = sorted(range(len(specs)), key=lambda i: specs[i]["nx"] * specs[i]["ny"])[:3]
+    for i in order:
+        say("  domain %d (%dx%d)" % (i, specs[i]["nx"], specs[i]["ny"]))
+        om = _oracle_for_spec(specs[i], steps)
+        gm = [t.cpu().numpy() for t in b.moments(i)]
+        assert_fp32(gm, om)
+
+
+def test_channel_profiles_match_startup_series():
+    """Secs. 7, 8: channels started from rest, FP32 batched form: u_y(x, t) follows
+    the Couette / Poiseuille start-up series and T(x, t) the conduction series
+    (halfway walls, xi = x + 1/2; nu, kappa from the derived coefficients)."""
+    lbm13 = _lb()
+    E0, dT = -2.0, 0.01
+    cases = [("couette", 32, 0.01, 0.0), ("couette", 48, 0.005, 0.0), ("poiseuille", 32, 0.0, 2e-6),
+             ("poiseuille", 40, 0.0, 1e-6)]
+    b = lbm13.Batch([(W, 8) for _, W, _, _ in cases], lbm13.FP32_DEV)
+    ders = []
+    for i, (kind, W, U, F) in enumerate(cases):
+        ders.append(b.set_params(i, sides=lbm13.make_sides((2, 2, 0, 0), (U, 0, 0, 0), (E0 + dT, E0 - dT, 0, 0)),
+                                 F0=(0.0, F)))
+        b.init_moments(i, *workloads.rest_fields(W, 8, E0))
+    steps = 3000
+    say("channel start-up profiles, %d steps" % steps)
+    b.step(steps)
+    for i, (kind, W, U, F) in enumerate(cases):
+        rho, ux, uy, T = [t.cpu().numpy()[4] for t in b.moments(i)]
+        xi = np.arange(W) + 0.5
+        nu, kappa = ders[i]["nu"], ders[i]["kappa"]
+        if kind == "couette":
+            ref = startup_couette(xi, W, U, nu, steps)
+            scale = U
+        else:
+            ref = startup_poiseuille(xi, W, F, nu, steps)
+            scale = F * W * W / (8 * nu)
+        assert np.abs(uy - ref).max() <= 0.02 * scale, (kind, W, np.abs(uy - ref).max() / scale)
+        assert np.abs(ux).max() <= 0.01 * scale
+        Tref = startup_conduction(xi, W, E0, dT, kappa, steps)
+        heat = 13 * 0.71 * max(U, scale) ** 2
+        assert np.abs(T - Tref).max() <= 0.03 * dT + heat, (kind, W, np.abs(T - Tref).max())

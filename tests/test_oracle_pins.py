@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
+from analytic import startup_conduction, startup_couette, startup_poiseuille
 from oracle import linear
 from paper_1401_0188_amd import workloads
 
@@ -458,3 +459,40 @@ def test_couette_wall_temperature_is_imposed():
     assert abs(T_west - p.E0) < 3e-5 and abs(T_east - p.E0) < 3e-5
     # viscous heating lifts the interior above the walls (compressible energy equation, sec. 3)
     assert T[0].max() - p.E0 > 1e-4
+
+
+@pytest.mark.parametrize("Pr", [0.5, 0.71, 1.0, 1.5, 3.0, 7.0])
+def test_cavity_parameter_sets_are_linearly_stable(Pr):
+    """The per-Pr parameter sets used for the batched cavities keep every linear
+    mode bounded (max |lambda| <= 1) at rest and with |u| <= 0.05 and |E - E0| <= 0.3."""
+    kw = workloads.cavity_parameter_set(Pr)
+    p = oracle.params(**kw)
+    assert oracle.derive(p)[0] == 0
+    for dE in (0.0, 0.3):
+        for U in ((0.0, 0.0), (0.05, 0.0), (0.035, 0.035)):
+            w = 0.0
+            for kx in np.linspace(0, np.pi, 11):
+                for ky in np.linspace(0, kx, 11):
+                    A = linear.amplification(p, (kx, ky), U, rho=1 - dE / 28, E=p.E0 + dE)
+                    w = max(w, float(np.abs(np.linalg.eigvals(A)).max()))
+            assert w <= 1 + 1e-9, (dE, U, w)
+
+
+@pytest.mark.parametrize("kind,W,U,F", [("couette", 32, 0.01, 0.0), ("poiseuille", 40, 0.0, 1e-6)])
+def test_channel_startup_follows_series(kind, W, U, F):
+    """Channels started from rest: u_y(x, t) follows the Couette / Poiseuille
+    start-up series with nu, and T(x, t) the conduction series with kappa
+    (temperature walls +- dT, sec. 7)."""
+    E0, dT, steps = -2.0, 0.01, 3000
+    p = oracle.params(F0y=F)
+    st, d = oracle.derive(p)
+    s = oracle.sides((2, 2, 0, 0), (U, 0, 0, 0), (E0 + dT, E0 - dT, 0, 0))
+    f = oracle.run(oracle.init(*workloads.rest_fields(W, 4, E0), p), p, s, steps)
+    rho, ux, uy, T = [a[2] for a in oracle.moments(f, p)]
+    xi = np.arange(W) + 0.5
+    if kind == "couette":
+        ref, scale = startup_couette(xi, W, U, d["nu"], steps), U
+    else:
+        ref, scale = startup_poiseuille(xi, W, F, d["nu"], steps), F * W * W / (8 * d["nu"])
+    assert np.abs(uy - ref).max() <= 5e-3 * scale
+    assert np.abs(T - startup_conduction(xi, W, E0, dT, d["kappa"], steps)).max() <= 1e-2 * dT
