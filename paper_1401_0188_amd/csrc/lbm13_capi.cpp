@@ -24,7 +24,8 @@
 
 namespace lbm13 {
 template <typename R>
-hipError_t launch_step(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, hipStream_t);
+hipError_t launch_step(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, const WallLine*, int,
+                       R*, hipStream_t);
 template <typename R>
 hipError_t launch_diag(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, double*, hipStream_t);
 template <typename R>
@@ -40,6 +41,7 @@ hipError_t launch_set_state(int, int, R*, const Dom<R>*, int, const double*, hip
 
 using lbm13::Dom;
 using lbm13::Tile;
+using lbm13::WallLine;
 
 namespace {
 
@@ -56,10 +58,12 @@ bool valid_shape(int tx, int ty) {
 }
 
 struct Layout {
-    size_t doms, coef, tiles_all, tiles_run, part, diag, bufA, bufB, total;
+    size_t doms, coef, tiles_all, tiles_run, part, diag, lines, wall, bufA, bufB, total;
     size_t buf_bytes;
     int tmax;
-    std::vector<long long> off;  // per-domain element offset
+    long long nlines_max;
+    std::vector<long long> off;   // per-domain element offset of the populations
+    std::vector<long long> woff;  // per-domain element offset of the wall terms
     std::vector<int> pitch, plane;
 };
 
@@ -69,9 +73,10 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
     const size_t es = precision == LBM13_FP64 ? 8 : 4;
     const size_t dom_size = precision == LBM13_FP64 ? sizeof(Dom<double>) : sizeof(Dom<float>);
     L.off.resize(count);
+    L.woff.resize(count);
     L.pitch.resize(count);
     L.plane.resize(count);
-    long long tmax = 0;
+    long long tmax = 0, lines = 0;
     size_t elems = 0;
     for (int d = 0; d < count; ++d) {
         if (nx[d] < 2 || ny[d] < 2 || nx[d] > (1 << 16) || ny[d] > (1 << 16)) return false;
@@ -82,6 +87,8 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
         L.plane[d] = (int)plane;
         L.off[d] = (long long)elems;
         elems += align_up(13 * plane, kAlign / es);
+        L.woff[d] = 13 * lines;
+        lines += 2LL * (nx[d] + ny[d]);
         long long t = 0;
         for (auto& s : kShapes)
             t = std::max(t, (long long)((nx[d] + s[0] - 1) / s[0]) * ((ny[d] + s[1] - 1) / s[1]));
@@ -96,6 +103,9 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
     L.tiles_run = p; p = align_up(p + sizeof(Tile) * tmax, kAlign);
     L.part = p;      p = align_up(p + sizeof(double) * lbm13::kDiagPartials * tmax, kAlign);
     L.diag = p;      p = align_up(p + sizeof(double) * lbm13::kDiagOut * count, kAlign);
+    L.nlines_max = lines;
+    L.lines = p;     p = align_up(p + sizeof(WallLine) * lines, kAlign);
+    L.wall = p;      p = align_up(p + es * 13 * lines, kAlign);
     L.buf_bytes = elems * es;
     L.bufA = p;      p = align_up(p + L.buf_bytes, kAlign);
     L.bufB = p;      p = align_up(p + L.buf_bytes, kAlign);
@@ -159,6 +169,7 @@ struct lbm13_batch {
     std::vector<int> sides_kind;          // 4 per domain
     std::vector<char> has_params, has_state;
     std::vector<Tile> all, run;
+    std::vector<WallLine> lines;
     int nbulk = 0, nedge = 0;
     int tile_x = 64, tile_y = 8;
     int cur = 0;                          // buffer holding the current state
@@ -251,6 +262,22 @@ int rebuild(lbm13_batch* b) {
     if ((int)b->all.size() > b->L.tmax) return fail(b, LBM13_EINVAL, "tile table overflow");
     b->run = bulk;
     b->run.insert(b->run.end(), edge.begin(), edge.end());
+    b->lines.clear();
+    for (int d = 0; d < b->count; ++d) {
+        const int* k = &b->sides_kind[4 * d];
+        const int nx = b->nx[d], ny = b->ny[d];
+        if (k[0] != LBM13_PERIODIC)
+            for (int y = 0; y < ny; ++y) {
+                b->lines.push_back(WallLine{d, 0, y, y});
+                b->lines.push_back(WallLine{d, 1, y, ny + y});
+            }
+        if (k[2] != LBM13_PERIODIC)
+            for (int x = 0; x < nx; ++x) {
+                b->lines.push_back(WallLine{d, 2, x, 2 * ny + x});
+                b->lines.push_back(WallLine{d, 3, x, 2 * ny + nx + x});
+            }
+    }
+    if ((long long)b->lines.size() > b->L.nlines_max) return fail(b, LBM13_EINVAL, "wall line table overflow");
     b->nbulk = (int)bulk.size();
     b->nedge = (int)edge.size();
     if (b->precision == LBM13_FP64) set_tile_ranges<double>(b);
@@ -262,6 +289,11 @@ int rebuild(lbm13_batch* b) {
     e = hipMemcpyAsync(b->ws + b->L.tiles_run, b->run.data(), sizeof(Tile) * b->run.size(), hipMemcpyHostToDevice,
                        b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "upload tile table");
+    if (!b->lines.empty()) {
+        e = hipMemcpyAsync(b->ws + b->L.lines, b->lines.data(), sizeof(WallLine) * b->lines.size(),
+                           hipMemcpyHostToDevice, b->stream);
+        if (e != hipSuccess) return hip_fail(b, e, "upload wall lines");
+    }
     e = hipMemcpyAsync(b->ws + b->L.doms, b->dom_host.data(), b->dom_host.size(), hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "upload domain table");
     e = hipStreamSynchronize(b->stream);
@@ -278,6 +310,7 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
     D->tile0 = tile0;
     D->ntiles = ntiles;
     D->off = b->L.off[d];
+    D->woff = b->L.woff[d];
     D->plane = b->L.plane[d];
     D->pitch = b->L.pitch[d];
     D->nx = b->nx[d];
@@ -332,10 +365,17 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
 bool check_index(lbm13_batch* b, int i) { return b && i >= 0 && i < b->count; }
 
 template <typename R>
-int do_step(lbm13_batch* b, int from) {
+hipError_t launch_one_step(lbm13_batch* b, int from, hipStream_t s) {
     const Tile* run = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_run);
-    hipError_t e = lbm13::launch_step<R>(b->tile_x, b->tile_y, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b),
-                                         run, b->nbulk, run + b->nbulk, b->nedge, b->stream);
+    const WallLine* lines = reinterpret_cast<const WallLine*>(b->ws + b->L.lines);
+    R* wterm = reinterpret_cast<R*>(b->ws + b->L.wall);
+    return lbm13::launch_step<R>(b->tile_x, b->tile_y, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), run,
+                                 b->nbulk, run + b->nbulk, b->nedge, lines, (int)b->lines.size(), wterm, s);
+}
+
+template <typename R>
+int do_step(lbm13_batch* b, int from) {
+    hipError_t e = launch_one_step<R>(b, from, b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "step launch");
     return LBM13_OK;
 }
@@ -349,12 +389,10 @@ int capture_graph(lbm13_batch* b, int parity) {
     }
     e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(b, e, "begin capture");
-    const Tile* run = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_run);
     int from = parity;
     hipError_t le = hipSuccess;
     for (int s = 0; s < b->graph_k && le == hipSuccess; ++s) {
-        le = lbm13::launch_step<R>(b->tile_x, b->tile_y, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), run,
-                                   b->nbulk, run + b->nbulk, b->nedge, b->capture_stream);
+        le = launch_one_step<R>(b, from, b->capture_stream);
         from = 1 - from;
     }
     hipGraph_t g = nullptr;

@@ -165,17 +165,38 @@ __device__ __forceinline__ void node_rho_E(const R* __restrict__ b, const Dom<R>
     E = e;
 }
 
-// Equilibrium moments (deviation from rest) of wall w on the wall-normal line
-// through (x, y), from the time-t state: rho_W = (3 rho_0 - rho_1)/2 of the
-// first two fluid layers, j_W = rho_W u_W along the wall, E_W imposed
-// (temperature wall) or E of layer 0 (adiabatic wall); sec. 7.
+// Whether link i crossing wall w is an anti-bounce-back link: normal to a
+// temperature wall (sec. 7: links with a tangential component bounce back).
+__device__ __forceinline__ bool abb_link(int kind, int w, int i) {
+    const bool normal = (w < 2) ? (c_vy[i] == 0) : (c_vx[i] == 0);
+    return normal && kind == kDirichletT;
+}
+
+// Wall terms, once per step before the step kernel: for every position along
+// every wall, the equilibrium moments of the wall state (deviation from rest)
+// from the time-t state -- rho_W = (3 rho_0 - rho_1)/2 of the first two fluid
+// layers on the wall-normal line, j_W = rho_W u_W along the wall, E_W imposed
+// (temperature wall) or E of layer 0 (adiabatic wall) -- and from them, for each
+// link i, the term added to the reflected population (eq d2q13-cl-abb):
+//   bounce-back:      2 sum_{k odd}  M_ki m_k(W) / D_k
+//   anti-bounce-back: 2 sum_{k even} M_ki m_k(W) / D_k
+// (deviations suffice: f^rest is even in v, so its odd part vanishes and its
+// even part cancels against the reflected rest population).
 template <typename R>
-__device__ void wall_moments(const R* __restrict__ b, const Dom<R>& D, int w, int x, int y, R m[13]) {
+__global__ __launch_bounds__(256) void wall_prep_kernel(const R* __restrict__ src, const Dom<R>* __restrict__ doms,
+                                                        const WallLine* __restrict__ lines, int nlines,
+                                                        R* __restrict__ wterm) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlines) return;
+    const WallLine wl = lines[l];
+    const Dom<R>& D = doms[wl.dom];
+    const R* __restrict__ b = src + D.off;
+    const int w = wl.w, pos = wl.pos;
     int c0, c1;
-    if (w == 0) { c0 = y * D.pitch; c1 = c0 + 1; }
-    else if (w == 1) { c0 = y * D.pitch + D.nx - 1; c1 = c0 - 1; }
-    else if (w == 2) { c0 = x; c1 = D.pitch + x; }
-    else { c0 = (D.ny - 1) * D.pitch + x; c1 = c0 - D.pitch; }
+    if (w == 0) { c0 = pos * D.pitch; c1 = c0 + 1; }
+    else if (w == 1) { c0 = pos * D.pitch + D.nx - 1; c1 = c0 - 1; }
+    else if (w == 2) { c0 = pos; c1 = D.pitch + pos; }
+    else { c0 = (D.ny - 1) * D.pitch + pos; c1 = c0 - D.pitch; }
     R r0, e0, r1, e1;
     node_rho_E(b, D, c0, r0, e0);
     node_rho_E(b, D, c1, r1, e1);
@@ -187,6 +208,7 @@ __device__ void wall_moments(const R* __restrict__ b, const Dom<R>& D, int w, in
     const R jy = (w < 2) ? jt : R(0);
     const R fq = D.a1 + D.h1 * rho + D.k1 * E;
     const R fr = D.a2 + D.h2 * rho + D.k2 * E;
+    R m[13];
     m[0] = rho;
     m[1] = E;
     m[2] = D.c_er * rho + D.c_eE * E;
@@ -200,22 +222,32 @@ __device__ void wall_moments(const R* __restrict__ b, const Dom<R>& D, int w, in
     m[10] = (jx * jx - jy * jy) / rhoW;
     m[11] = jx * jy / rhoW;
     m[12] = R(0);
+    R* __restrict__ o = wterm + D.woff + (long long)wl.line * 13;
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        const bool abb = abb_link(D.kind[w], w, i);
+        R t = R(0);
+#pragma unroll
+        for (int k = 0; k < 13; ++k) {
+            const bool odd = (k >= 4 && k <= 9);
+            if (abb != odd) t += R(c_M[k][i]) * m[k] / R(c_D[k]);
+        }
+        o[i] = R(2) * t;
+    }
 }
 
 // Gather for a node within two nodes of a wall: links whose source lies beyond
 // a wall come back along their reversed path from x' (tangential coordinate of
-// x kept, normal coordinate reflected through the wall), with
-//   bounce-back:      g_i = g*_opp(x') + 2 sum_{k odd}  M_ki m_k(W) / D_k
-//   anti-bounce-back: g_i = -g*_opp(x') + 2 sum_{k even} M_ki m_k(W) / D_k
-// (eq d2q13-cl-abb; deviations, since f^rest is even in v).  When a diagonal
-// source lies beyond two walls, the West/East wall applies.
+// x kept, normal coordinate reflected through the wall x_w: x' = 2 x_w + v - x),
+//   bounce-back:      g_i = g*_opp(x') + term_i(W)
+//   anti-bounce-back: g_i = -g*_opp(x') + term_i(W)
+// with the wall terms prepared for this step.  When a diagonal source lies
+// beyond two walls, the West/East wall applies.
 template <typename R>
-__device__ void gather_wall(const R* __restrict__ b, const Dom<R>& D, int x, int y, R g[13]) {
+__device__ __forceinline__ void gather_wall(const R* __restrict__ b, const R* __restrict__ wt, const Dom<R>& D,
+                                            int x, int y, R g[13]) {
     const int P = D.pitch, S = D.plane;
-    R mw[2][13];
-    bool have[2] = {false, false};
-    int widx[2] = {-1, -1};
-#pragma unroll 1
+#pragma unroll
     for (int i = 0; i < 13; ++i) {
         const int vx = c_vx[i], vy = c_vy[i];
         int sx = x - vx, sy = y - vy;
@@ -228,29 +260,16 @@ __device__ void gather_wall(const R* __restrict__ b, const Dom<R>& D, int x, int
         else if (w < 0 && sy >= D.ny) w = 3;
         if (w < 0) {
             g[i] = b[i * S + sy * P + sx];
-            continue;
+        } else {
+            int px = x, py = y, line;
+            if (w == 0) { px = -1 + vx - x; line = y; }
+            else if (w == 1) { px = 2 * D.nx - 1 + vx - x; line = D.ny + y; }
+            else if (w == 2) { py = -1 + vy - y; line = 2 * D.ny + x; }
+            else { py = 2 * D.ny - 1 + vy - y; line = 2 * D.ny + D.nx + x; }
+            const R src = b[c_opp[i] * S + py * P + px];
+            const R term = wt[line * 13 + i];
+            g[i] = (abb_link(D.kind[w], w, i) ? -src : src) + term;
         }
-        int px = x, py = y;
-        if (w == 0) px = -1 + vx - x;
-        else if (w == 1) px = 2 * D.nx - 1 + vx - x;
-        else if (w == 2) py = -1 + vy - y;
-        else py = 2 * D.ny - 1 + vy - y;
-        const R src = b[c_opp[i] * S + py * P + px];
-        const int slot = (w < 2) ? 0 : 1;
-        if (!have[slot] || widx[slot] != w) {
-            wall_moments(b, D, w, x, y, mw[slot]);
-            have[slot] = true;
-            widx[slot] = w;
-        }
-        const bool normal = (w < 2) ? (vy == 0) : (vx == 0);
-        const bool abb = normal && D.kind[w] == kDirichletT;
-        R extra = R(0);
-#pragma unroll
-        for (int k = 0; k < 13; ++k) {
-            const bool odd = (k >= 4 && k <= 9);
-            if (abb != odd) extra += R(c_M[k][i]) * mw[slot][k] / R(c_D[k]);
-        }
-        g[i] = (abb ? -src : src) + R(2) * extra;
     }
 }
 
@@ -275,7 +294,8 @@ __device__ __forceinline__ void store_node(R* __restrict__ b, int S, int c, cons
 template <typename R, int TX, int RPT, bool WALLS>
 __global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R* __restrict__ dst,
                                                    const Dom<R>* __restrict__ doms,
-                                                   const Tile* __restrict__ tiles, int ntiles) {
+                                                   const Tile* __restrict__ tiles, int ntiles,
+                                                   const R* __restrict__ wterm) {
     constexpr int TYB = 256 / TX;
     const int t = xcd_tile(blockIdx.x, ntiles);
     const Tile tl = tiles[t];
@@ -290,7 +310,7 @@ __global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R*
         R g[13];
         if (WALLS) {
             const bool near = (!D.xper && (x < 2 || x >= D.nx - 2)) || (!D.yper && (y < 2 || y >= D.ny - 2));
-            if (near) gather_wall(a, D, x, y, g);
+            if (near) gather_wall(a, wterm + D.woff, D, x, y, g);
             else gather_bulk(a, D, x, y, g);
         } else {
             gather_bulk(a, D, x, y, g);
@@ -575,21 +595,26 @@ __global__ __launch_bounds__(256) void diag_final_kernel(const Dom<R>* __restric
 
 template <typename R, int TX, int RPT>
 static hipError_t launch_step_t(const R* src, R* dst, const Dom<R>* doms, const Tile* bulk, int nbulk,
-                                const Tile* edge, int nedge, hipStream_t s) {
+                                const Tile* edge, int nedge, const WallLine* lines, int nlines, R* wterm,
+                                hipStream_t s) {
     constexpr dim3 blk(TX, 256 / TX);
-    if (nbulk > 0) step_kernel<R, TX, RPT, false><<<nbulk, blk, 0, s>>>(src, dst, doms, bulk, nbulk);
-    if (nedge > 0) step_kernel<R, TX, RPT, true><<<nedge, blk, 0, s>>>(src, dst, doms, edge, nedge);
+    if (nlines > 0) wall_prep_kernel<R><<<(nlines + 255) / 256, 256, 0, s>>>(src, doms, lines, nlines, wterm);
+    if (nbulk > 0) step_kernel<R, TX, RPT, false><<<nbulk, blk, 0, s>>>(src, dst, doms, bulk, nbulk, wterm);
+    if (nedge > 0) step_kernel<R, TX, RPT, true><<<nedge, blk, 0, s>>>(src, dst, doms, edge, nedge, wterm);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_step(int tile_x, int tile_y, const R* src, R* dst, const Dom<R>* doms, const Tile* bulk,
-                       int nbulk, const Tile* edge, int nedge, hipStream_t s) {
-    if (tile_x == 64 && tile_y == 4) return launch_step_t<R, 64, 1>(src, dst, doms, bulk, nbulk, edge, nedge, s);
-    if (tile_x == 64 && tile_y == 8) return launch_step_t<R, 64, 2>(src, dst, doms, bulk, nbulk, edge, nedge, s);
-    if (tile_x == 64 && tile_y == 16) return launch_step_t<R, 64, 4>(src, dst, doms, bulk, nbulk, edge, nedge, s);
-    if (tile_x == 32 && tile_y == 8) return launch_step_t<R, 32, 1>(src, dst, doms, bulk, nbulk, edge, nedge, s);
-    if (tile_x == 32 && tile_y == 16) return launch_step_t<R, 32, 2>(src, dst, doms, bulk, nbulk, edge, nedge, s);
+                       int nbulk, const Tile* edge, int nedge, const WallLine* lines, int nlines, R* wterm,
+                       hipStream_t s) {
+#define LBM13_STEP_ARGS src, dst, doms, bulk, nbulk, edge, nedge, lines, nlines, wterm, s
+    if (tile_x == 64 && tile_y == 4) return launch_step_t<R, 64, 1>(LBM13_STEP_ARGS);
+    if (tile_x == 64 && tile_y == 8) return launch_step_t<R, 64, 2>(LBM13_STEP_ARGS);
+    if (tile_x == 64 && tile_y == 16) return launch_step_t<R, 64, 4>(LBM13_STEP_ARGS);
+    if (tile_x == 32 && tile_y == 8) return launch_step_t<R, 32, 1>(LBM13_STEP_ARGS);
+    if (tile_x == 32 && tile_y == 16) return launch_step_t<R, 32, 2>(LBM13_STEP_ARGS);
+#undef LBM13_STEP_ARGS
     return hipErrorInvalidValue;
 }
 
@@ -644,7 +669,7 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
 
 #define LBM13_INSTANTIATE(R)                                                                                      \
     template hipError_t launch_step<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, \
-                                       hipStream_t);                                                              \
+                                       const WallLine*, int, R*, hipStream_t);                                    \
     template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*,         \
                                        double*, hipStream_t);                                                     \
     template hipError_t launch_init<R>(int, int, R*, const Dom<R>*, int, const double*, const double*,           \
