@@ -24,8 +24,10 @@
 
 namespace lbm13 {
 template <typename R>
-hipError_t launch_step(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, const WallLine*, int,
-                       R*, hipStream_t);
+hipError_t launch_step(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, R*, int,
+                       hipStream_t);
+template <typename R>
+hipError_t launch_side_fill(const R*, const Dom<R>*, const WallLine*, int, R*, int, hipStream_t);
 template <typename R>
 hipError_t launch_diag(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, double*, hipStream_t);
 template <typename R>
@@ -63,7 +65,7 @@ struct Layout {
     int tmax;
     long long nlines_max;
     std::vector<long long> off;   // per-domain element offset of the populations
-    std::vector<long long> woff;  // per-domain element offset of the wall terms
+    std::vector<long long> woff;  // per-domain element offset of the wall-layer side array
     std::vector<int> pitch, plane;
 };
 
@@ -87,7 +89,7 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
         L.plane[d] = (int)plane;
         L.off[d] = (long long)elems;
         elems += align_up(13 * plane, kAlign / es);
-        L.woff[d] = 13 * lines;
+        L.woff[d] = 8 * lines;  // 2 buffers x 2 (nx + ny) lines x 4 values
         lines += 2LL * (nx[d] + ny[d]);
         long long t = 0;
         for (auto& s : kShapes)
@@ -105,7 +107,7 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
     L.diag = p;      p = align_up(p + sizeof(double) * lbm13::kDiagOut * count, kAlign);
     L.nlines_max = lines;
     L.lines = p;     p = align_up(p + sizeof(WallLine) * lines, kAlign);
-    L.wall = p;      p = align_up(p + es * 13 * lines, kAlign);
+    L.wall = p;      p = align_up(p + es * 8 * lines, kAlign);
     L.buf_bytes = elems * es;
     L.bufA = p;      p = align_up(p + L.buf_bytes, kAlign);
     L.bufB = p;      p = align_up(p + L.buf_bytes, kAlign);
@@ -367,10 +369,22 @@ bool check_index(lbm13_batch* b, int i) { return b && i >= 0 && i < b->count; }
 template <typename R>
 hipError_t launch_one_step(lbm13_batch* b, int from, hipStream_t s) {
     const Tile* run = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_run);
-    const WallLine* lines = reinterpret_cast<const WallLine*>(b->ws + b->L.lines);
-    R* wterm = reinterpret_cast<R*>(b->ws + b->L.wall);
+    R* side = reinterpret_cast<R*>(b->ws + b->L.wall);
     return lbm13::launch_step<R>(b->tile_x, b->tile_y, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), run,
-                                 b->nbulk, run + b->nbulk, b->nedge, lines, (int)b->lines.size(), wterm, s);
+                                 b->nbulk, run + b->nbulk, b->nedge, side, from, s);
+}
+
+// Wall-layer side values of the kept state (after init, set_state, load).
+template <typename R>
+hipError_t fill_side(lbm13_batch* b) {
+    const WallLine* lines = reinterpret_cast<const WallLine*>(b->ws + b->L.lines);
+    R* side = reinterpret_cast<R*>(b->ws + b->L.wall);
+    return lbm13::launch_side_fill<R>(buf<R>(b, b->cur), doms_dev<R>(b), lines, (int)b->lines.size(), side, b->cur,
+                                      b->stream);
+}
+
+hipError_t fill_side_any(lbm13_batch* b) {
+    return b->precision == LBM13_FP64 ? fill_side<double>(b) : fill_side<float>(b);
 }
 
 template <typename R>
@@ -554,7 +568,15 @@ int lbm13_batch_set_params(lbm13_batch* b, int i, const lbm13_params* p, const l
                                   sizeof(double) * kCoef, hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "upload coefficients");
     b->has_params[i] = 1;
-    return rebuild(b);
+    st = rebuild(b);
+    if (st) return st;
+    bool any_state = false;
+    for (char h : b->has_state) any_state = any_state || h;
+    if (any_state) {
+        e = fill_side_any(b);  // walls may have changed under a kept state
+        if (e != hipSuccess) return hip_fail(b, e, "side fill launch");
+    }
+    return LBM13_OK;
 }
 
 int lbm13_batch_init_moments(lbm13_batch* b, int i, const double* rho, const double* ux, const double* uy,
@@ -570,6 +592,8 @@ int lbm13_batch_init_moments(lbm13_batch* b, int i, const double* rho, const dou
         e = lbm13::launch_init<float>(b->nx[i], b->ny[i], buf<float>(b, b->cur), doms_dev<float>(b), i, rho, ux, uy, T,
                                       coef, b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "init launch");
+    e = fill_side_any(b);
+    if (e != hipSuccess) return hip_fail(b, e, "side fill launch");
     b->has_state[i] = 1;
     b->steps = 0;
     return LBM13_OK;
@@ -645,6 +669,8 @@ int lbm13_batch_set_state(lbm13_batch* b, int i, const double* src) {
         e = lbm13::launch_set_state<float>(b->nx[i], b->ny[i], buf<float>(b, b->cur), doms_dev<float>(b), i, src,
                                            b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "set_state launch");
+    e = fill_side_any(b);
+    if (e != hipSuccess) return hip_fail(b, e, "side fill launch");
     b->has_state[i] = 1;
     return LBM13_OK;
 }
@@ -683,8 +709,11 @@ int lbm13_batch_load(lbm13_batch* b, int i, const void* src) {
     if (!check_index(b, i) || !src) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
     if (!b->has_params[i]) return fail(b, LBM13_ESTATE, "set_params first");
     int st = raw_copy(b, i, nullptr, src);
-    if (st == LBM13_OK) b->has_state[i] = 1;
-    return st;
+    if (st != LBM13_OK) return st;
+    hipError_t e = fill_side_any(b);
+    if (e != hipSuccess) return hip_fail(b, e, "side fill launch");
+    b->has_state[i] = 1;
+    return LBM13_OK;
 }
 
 int lbm13_batch_set_tile(lbm13_batch* b, int tile_x, int tile_y) {

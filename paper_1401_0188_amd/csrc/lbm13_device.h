@@ -18,7 +18,7 @@ enum SideKind { kPeriodic = 0, kAdiabatic = 1, kDirichletT = 2 };
 template <typename R>
 struct alignas(16) Dom {
     long long off;    // element offset of plane 0 of this domain in each population buffer
-    long long woff;   // element offset of this domain's wall terms (2 (nx + ny) lines x 13)
+    long long woff;   // element offset of this domain's wall-layer side array: 2 buffers x 2 (nx + ny) lines x 4
     int plane;        // elements between two velocity planes
     int pitch;        // elements between two rows
     int nx, ny;
@@ -54,7 +54,8 @@ struct alignas(16) Tile {
 
 // One wall line: the position `pos` along wall `w` (0 W, 1 E, 2 S, 3 N) of
 // domain `dom`; `line` is its index among the domain's 2 (nx + ny) lines
-// (W: y, E: ny + y, S: 2 ny + x, N: 2 ny + nx + x).
+// (W: y, E: ny + y, S: 2 ny + x, N: 2 ny + nx + x).  Each line keeps, per
+// state buffer, (rho', E') of the first fluid layer and rho' of the second.
 struct alignas(16) WallLine {
     int dom, w, pos, line;
 };

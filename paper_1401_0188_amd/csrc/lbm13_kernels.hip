@@ -41,6 +41,8 @@ __constant__ float c_M[13][13] = {
     {0, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0},
     {0, -4, 4, -4, 4, 0, 0, 0, 0, 1, -1, 1, -1}};
 __constant__ float c_D[13] = {13, 4004, 42196, 548, 14, 14, 20, 20, 70, 70, 68, 4, 68};
+__constant__ double c_invD[13] = {1.0 / 13, 1.0 / 4004, 1.0 / 42196, 1.0 / 548, 1.0 / 14, 1.0 / 14, 1.0 / 20,
+                                  1.0 / 20, 1.0 / 70, 1.0 / 70, 1.0 / 68, 1.0 / 4, 1.0 / 68};
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -172,20 +174,19 @@ __device__ __forceinline__ bool abb_link(int kind, int w, int i) {
     return normal && kind == kDirichletT;
 }
 
-// Wall terms, once per step before the step kernel: for every position along
-// every wall, the equilibrium moments of the wall state (deviation from rest)
-// from the time-t state -- rho_W = (3 rho_0 - rho_1)/2 of the first two fluid
-// layers on the wall-normal line, j_W = rho_W u_W along the wall, E_W imposed
-// (temperature wall) or E of layer 0 (adiabatic wall) -- and from them, for each
-// link i, the term added to the reflected population (eq d2q13-cl-abb):
-//   bounce-back:      2 sum_{k odd}  M_ki m_k(W) / D_k
-//   anti-bounce-back: 2 sum_{k even} M_ki m_k(W) / D_k
-// (deviations suffice: f^rest is even in v, so its odd part vanishes and its
-// even part cancels against the reflected rest population).
+// Side array of the wall layers: for every position along every wall, rho' and
+// E' of the first fluid layer and rho' of the second, for the state kept in
+// buffer `buf` (the step kernel writes them for the state it produces).
 template <typename R>
-__global__ __launch_bounds__(256) void wall_prep_kernel(const R* __restrict__ src, const Dom<R>* __restrict__ doms,
+__device__ __forceinline__ R* side_line(R* side, const Dom<R>& D, int buf, int line) {
+    return side + D.woff + (long long)buf * (2 * (D.nx + D.ny)) * 4 + line * 4;
+}
+
+// Fill the side array from a stored state (after init, set_state or load).
+template <typename R>
+__global__ __launch_bounds__(256) void side_fill_kernel(const R* __restrict__ src, const Dom<R>* __restrict__ doms,
                                                         const WallLine* __restrict__ lines, int nlines,
-                                                        R* __restrict__ wterm) {
+                                                        R* __restrict__ side, int buf) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nlines) return;
     const WallLine wl = lines[l];
@@ -200,76 +201,188 @@ __global__ __launch_bounds__(256) void wall_prep_kernel(const R* __restrict__ sr
     R r0, e0, r1, e1;
     node_rho_E(b, D, c0, r0, e0);
     node_rho_E(b, D, c1, r1, e1);
-    const R rho = R(1.5) * r0 - R(0.5) * r1;
-    const R E = (D.kind[w] == kDirichletT) ? D.wall_dE[w] : e0;
+    R* o = side_line(side, D, buf, wl.line);
+    o[0] = r0;
+    o[1] = e0;
+    o[2] = r1;
+    o[3] = R(0);
+}
+
+// Compile-time copy of the moment matrix for the wall fix-ups (same rows as c_M).
+constexpr int kM[13][13] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-28, -15, -15, -15, -15, -2, -2, -2, -2, 24, 24, 24, 24},
+    {140, -2, -2, -2, -2, -67, -67, -67, -67, 34, 34, 34, 34},
+    {-12, 8, 8, 8, 8, -6, -6, -6, -6, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2},
+    {0, -2, 0, 2, 0, -1, 1, 1, -1, 2, 0, -2, 0},
+    {0, 0, -2, 0, 2, -1, -1, 1, 1, 0, 2, 0, -2},
+    {0, 4, 0, -4, 0, -3, 3, 3, -3, 1, 0, -1, 0},
+    {0, 0, 4, 0, -4, -3, -3, 3, 3, 0, 1, 0, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0, 4, -4, 4, -4},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, -4, 4, -4, 4, 0, 0, 0, 0, 1, -1, 1, -1}};
+constexpr int kVX[13] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0};
+constexpr int kVY[13] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2};
+constexpr int kOPP[13] = {0, 3, 4, 1, 2, 7, 8, 5, 6, 11, 12, 9, 10};
+
+// Equilibrium moments of a wall state, pre-divided by the norms D_k, as
+// deviations from rest (eq d2q13-moments-equil; sec. 7: rho_W = (3 rho_0 -
+// rho_1)/2 from the first two fluid layers at time t, j_W = rho_W u_W along the
+// wall, E_W imposed on a temperature wall or E of the first layer on an
+// adiabatic wall).  even: rho, E, eps, varpi, XX, XY; odd: jx, jy, qx, qy, rx, ry.
+template <typename R>
+struct WallState {
+    R even[6], odd[6];
+};
+
+template <typename R>
+__device__ __forceinline__ WallState<R> wall_state(const Dom<R>& D, int w, R rho0, R E0l, R rho1) {
+    WallState<R> ws;
+    const R rho = R(1.5) * rho0 - R(0.5) * rho1;
+    const R E = (D.kind[w] == kDirichletT) ? D.wall_dE[w] : E0l;
+    const R u = D.wall_u[w];
     const R rhoW = R(1) + rho;
-    const R jt = rhoW * D.wall_u[w];
+    const R jt = rhoW * u;
     const R jx = (w < 2) ? R(0) : jt;
     const R jy = (w < 2) ? jt : R(0);
+    const R inv = (u != R(0)) ? R(1) / rhoW : R(0);
+    ws.even[0] = rho * R(1.0 / 13.0);
+    ws.even[1] = E * R(1.0 / 4004.0);
+    ws.even[2] = (D.c_er * rho + D.c_eE * E) * R(1.0 / 42196.0);
+    ws.even[3] = (D.c_vr * rho + D.c_vE * E) * R(1.0 / 548.0);
+    ws.even[4] = (jx * jx - jy * jy) * inv * R(1.0 / 68.0);
+    ws.even[5] = jx * jy * inv * R(0.25);
     const R fq = D.a1 + D.h1 * rho + D.k1 * E;
     const R fr = D.a2 + D.h2 * rho + D.k2 * E;
-    R m[13];
-    m[0] = rho;
-    m[1] = E;
-    m[2] = D.c_er * rho + D.c_eE * E;
-    m[3] = D.c_vr * rho + D.c_vE * E;
-    m[4] = jx;
-    m[5] = jy;
-    m[6] = jx * fq;
-    m[7] = jy * fq;
-    m[8] = jx * fr;
-    m[9] = jy * fr;
-    m[10] = (jx * jx - jy * jy) / rhoW;
-    m[11] = jx * jy / rhoW;
-    m[12] = R(0);
-    R* __restrict__ o = wterm + D.woff + (long long)wl.line * 13;
-#pragma unroll
-    for (int i = 0; i < 13; ++i) {
-        const bool abb = abb_link(D.kind[w], w, i);
-        R t = R(0);
-#pragma unroll
-        for (int k = 0; k < 13; ++k) {
-            const bool odd = (k >= 4 && k <= 9);
-            if (abb != odd) t += R(c_M[k][i]) * m[k] / R(c_D[k]);
-        }
-        o[i] = R(2) * t;
+    ws.odd[0] = jx * R(1.0 / 14.0);
+    ws.odd[1] = jy * R(1.0 / 14.0);
+    ws.odd[2] = jx * fq * R(0.05);
+    ws.odd[3] = jy * fq * R(0.05);
+    ws.odd[4] = jx * fr * R(1.0 / 70.0);
+    ws.odd[5] = jy * fr * R(1.0 / 70.0);
+    return ws;
+}
+
+// Term added to the reflected population of link I (eq d2q13-cl-abb):
+//   bounce-back:      2 sum_{k odd}  M_kI m_k(W) / D_k
+//   anti-bounce-back: 2 sum_{k even} M_kI m_k(W) / D_k
+// f^rest is even in v, so its odd part vanishes and its even part cancels
+// against the reflected rest population: deviations need no other correction.
+template <int I, typename R>
+__device__ __forceinline__ R wall_term(const WallState<R>& ws, bool abb) {
+    if (abb)
+        return R(2) * (R(kM[0][I]) * ws.even[0] + R(kM[1][I]) * ws.even[1] + R(kM[2][I]) * ws.even[2] +
+                       R(kM[3][I]) * ws.even[3] + R(kM[10][I]) * ws.even[4] + R(kM[11][I]) * ws.even[5]);
+    return R(2) * (R(kM[4][I]) * ws.odd[0] + R(kM[5][I]) * ws.odd[1] + R(kM[6][I]) * ws.odd[2] +
+                   R(kM[7][I]) * ws.odd[3] + R(kM[8][I]) * ws.odd[4] + R(kM[9][I]) * ws.odd[5]);
+}
+
+// Replace link I, whose source lies beyond wall w, by its reversed path from x'
+// (tangential coordinate kept, normal coordinate reflected through the wall).
+template <int I, typename R>
+__device__ __forceinline__ void fix_link(const R* __restrict__ b, const Dom<R>& D, int w, int x, int y,
+                                         const WallState<R>& ws, R g[13]) {
+    int px = x, py = y;
+    if (w == 0) px = -1 + kVX[I] - x;
+    else if (w == 1) px = 2 * D.nx - 1 + kVX[I] - x;
+    else if (w == 2) py = -1 + kVY[I] - y;
+    else py = 2 * D.ny - 1 + kVY[I] - y;
+    const R src = b[kOPP[I] * D.plane + py * D.pitch + px];
+    const bool normal = (w < 2) ? (kVY[I] == 0) : (kVX[I] == 0);
+    const bool abb = normal && D.kind[w] == kDirichletT;
+    g[I] = (abb ? -src : src) + wall_term<I>(ws, abb);
+}
+
+// Gather for a node within two nodes of a wall: every link is first read with
+// clamped (in-bounds) coordinates, then the links whose source lies beyond a
+// wall are replaced (bounce-back for links with a tangential component and for
+// every link at an adiabatic wall, anti-bounce-back for links normal to a
+// temperature wall; sec. 7).  y walls are applied first and x walls last, so a
+// diagonal source beyond two walls takes the West/East wall.
+template <typename R>
+__device__ __forceinline__ void gather_wall(const R* __restrict__ b, const R* __restrict__ side, const Dom<R>& D,
+                                            int buf, int x, int y, R g[13]) {
+    const int P = D.pitch, S = D.plane;
+    int xm1 = x - 1, xm2 = x - 2, xp1 = x + 1, xp2 = x + 2;
+    int ym1 = y - 1, ym2 = y - 2, yp1 = y + 1, yp2 = y + 2;
+    if (D.xper) {
+        xm1 = wrap(xm1, D.nx); xm2 = wrap(xm2, D.nx); xp1 = wrap(xp1, D.nx); xp2 = wrap(xp2, D.nx);
+    } else {
+        xm1 = max(xm1, 0); xm2 = max(xm2, 0); xp1 = min(xp1, D.nx - 1); xp2 = min(xp2, D.nx - 1);
+    }
+    if (D.yper) {
+        ym1 = wrap(ym1, D.ny); ym2 = wrap(ym2, D.ny); yp1 = wrap(yp1, D.ny); yp2 = wrap(yp2, D.ny);
+    } else {
+        ym1 = max(ym1, 0); ym2 = max(ym2, 0); yp1 = min(yp1, D.ny - 1); yp2 = min(yp2, D.ny - 1);
+    }
+    const int r0 = y * P, rm1 = ym1 * P, rm2 = ym2 * P, rp1 = yp1 * P, rp2 = yp2 * P;
+    g[0] = b[r0 + x];
+    g[1] = b[1 * S + r0 + xm1];
+    g[2] = b[2 * S + rm1 + x];
+    g[3] = b[3 * S + r0 + xp1];
+    g[4] = b[4 * S + rp1 + x];
+    g[5] = b[5 * S + rm1 + xm1];
+    g[6] = b[6 * S + rm1 + xp1];
+    g[7] = b[7 * S + rp1 + xp1];
+    g[8] = b[8 * S + rp1 + xm1];
+    g[9] = b[9 * S + r0 + xm2];
+    g[10] = b[10 * S + rm2 + x];
+    g[11] = b[11 * S + r0 + xp2];
+    g[12] = b[12 * S + rp2 + x];
+    R* sd = const_cast<R*>(side);
+    if (!D.yper && y < 2) {  // South wall: links with v_y > 0
+        const R* p = side_line(sd, D, buf, 2 * D.ny + x);
+        const WallState<R> ws = wall_state(D, 2, p[0], p[1], p[2]);
+        if (y == 0) { fix_link<2>(b, D, 2, x, y, ws, g); fix_link<5>(b, D, 2, x, y, ws, g); fix_link<6>(b, D, 2, x, y, ws, g); }
+        fix_link<10>(b, D, 2, x, y, ws, g);
+    }
+    if (!D.yper && y >= D.ny - 2) {  // North wall: links with v_y < 0
+        const R* p = side_line(sd, D, buf, 2 * D.ny + D.nx + x);
+        const WallState<R> ws = wall_state(D, 3, p[0], p[1], p[2]);
+        if (y == D.ny - 1) { fix_link<4>(b, D, 3, x, y, ws, g); fix_link<7>(b, D, 3, x, y, ws, g); fix_link<8>(b, D, 3, x, y, ws, g); }
+        fix_link<12>(b, D, 3, x, y, ws, g);
+    }
+    if (!D.xper && x < 2) {  // West wall: links with v_x > 0
+        const R* p = side_line(sd, D, buf, y);
+        const WallState<R> ws = wall_state(D, 0, p[0], p[1], p[2]);
+        if (x == 0) { fix_link<1>(b, D, 0, x, y, ws, g); fix_link<5>(b, D, 0, x, y, ws, g); fix_link<8>(b, D, 0, x, y, ws, g); }
+        fix_link<9>(b, D, 0, x, y, ws, g);
+    }
+    if (!D.xper && x >= D.nx - 2) {  // East wall: links with v_x < 0
+        const R* p = side_line(sd, D, buf, D.ny + y);
+        const WallState<R> ws = wall_state(D, 1, p[0], p[1], p[2]);
+        if (x == D.nx - 1) { fix_link<3>(b, D, 1, x, y, ws, g); fix_link<6>(b, D, 1, x, y, ws, g); fix_link<7>(b, D, 1, x, y, ws, g); }
+        fix_link<11>(b, D, 1, x, y, ws, g);
     }
 }
 
-// Gather for a node within two nodes of a wall: links whose source lies beyond
-// a wall come back along their reversed path from x' (tangential coordinate of
-// x kept, normal coordinate reflected through the wall x_w: x' = 2 x_w + v - x),
-//   bounce-back:      g_i = g*_opp(x') + term_i(W)
-//   anti-bounce-back: g_i = -g*_opp(x') + term_i(W)
-// with the wall terms prepared for this step.  When a diagonal source lies
-// beyond two walls, the West/East wall applies.
+// After collision, a node in the first or second layer of a wall records its
+// rho' (and E' for the first layer) for the next step's wall states.
 template <typename R>
-__device__ __forceinline__ void gather_wall(const R* __restrict__ b, const R* __restrict__ wt, const Dom<R>& D,
-                                            int x, int y, R g[13]) {
-    const int P = D.pitch, S = D.plane;
+__device__ __forceinline__ void record_wall_layers(R* __restrict__ side, const Dom<R>& D, int buf, int x, int y,
+                                                   const R g[13]) {
+    const bool xw = !D.xper && (x < 2 || x >= D.nx - 2);
+    const bool yw = !D.yper && (y < 2 || y >= D.ny - 2);
+    if (!xw && !yw) return;
+    R rho = R(0), E = R(0);
 #pragma unroll
     for (int i = 0; i < 13; ++i) {
-        const int vx = c_vx[i], vy = c_vy[i];
-        int sx = x - vx, sy = y - vy;
-        int w = -1;
-        if (D.xper) sx = wrap(sx, D.nx);
-        else if (sx < 0) w = 0;
-        else if (sx >= D.nx) w = 1;
-        if (D.yper) sy = wrap(sy, D.ny);
-        else if (w < 0 && sy < 0) w = 2;
-        else if (w < 0 && sy >= D.ny) w = 3;
-        if (w < 0) {
-            g[i] = b[i * S + sy * P + sx];
-        } else {
-            int px = x, py = y, line;
-            if (w == 0) { px = -1 + vx - x; line = y; }
-            else if (w == 1) { px = 2 * D.nx - 1 + vx - x; line = D.ny + y; }
-            else if (w == 2) { py = -1 + vy - y; line = 2 * D.ny + x; }
-            else { py = 2 * D.ny - 1 + vy - y; line = 2 * D.ny + D.nx + x; }
-            const R src = b[c_opp[i] * S + py * P + px];
-            const R term = wt[line * 13 + i];
-            g[i] = (abb_link(D.kind[w], w, i) ? -src : src) + term;
-        }
+        rho += g[i];
+        E += R(c_M[1][i]) * g[i];
+    }
+    if (xw) {
+        if (x == 0) { R* p = side_line(side, D, buf, y); p[0] = rho; p[1] = E; }
+        if (x == 1) side_line(side, D, buf, y)[2] = rho;
+        if (x == D.nx - 1) { R* p = side_line(side, D, buf, D.ny + y); p[0] = rho; p[1] = E; }
+        if (x == D.nx - 2) side_line(side, D, buf, D.ny + y)[2] = rho;
+    }
+    if (yw) {
+        if (y == 0) { R* p = side_line(side, D, buf, 2 * D.ny + x); p[0] = rho; p[1] = E; }
+        if (y == 1) side_line(side, D, buf, 2 * D.ny + x)[2] = rho;
+        if (y == D.ny - 1) { R* p = side_line(side, D, buf, 2 * D.ny + D.nx + x); p[0] = rho; p[1] = E; }
+        if (y == D.ny - 2) side_line(side, D, buf, 2 * D.ny + D.nx + x)[2] = rho;
     }
 }
 
@@ -295,7 +408,7 @@ template <typename R, int TX, int RPT, bool WALLS>
 __global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R* __restrict__ dst,
                                                    const Dom<R>* __restrict__ doms,
                                                    const Tile* __restrict__ tiles, int ntiles,
-                                                   const R* __restrict__ wterm) {
+                                                   R* __restrict__ side, int from) {
     constexpr int TYB = 256 / TX;
     const int t = xcd_tile(blockIdx.x, ntiles);
     const Tile tl = tiles[t];
@@ -310,13 +423,14 @@ __global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R*
         R g[13];
         if (WALLS) {
             const bool near = (!D.xper && (x < 2 || x >= D.nx - 2)) || (!D.yper && (y < 2 || y >= D.ny - 2));
-            if (near) gather_wall(a, wterm + D.woff, D, x, y, g);
+            if (near) gather_wall(a, side, D, from, x, y, g);
             else gather_bulk(a, D, x, y, g);
         } else {
             gather_bulk(a, D, x, y, g);
         }
         if (D.collide) collide(g, D);
         store_node(o, D.plane, y * D.pitch + x, g);
+        if (WALLS) record_wall_layers(side, D, 1 - from, x, y, g);
     }
 }
 
@@ -595,20 +709,17 @@ __global__ __launch_bounds__(256) void diag_final_kernel(const Dom<R>* __restric
 
 template <typename R, int TX, int RPT>
 static hipError_t launch_step_t(const R* src, R* dst, const Dom<R>* doms, const Tile* bulk, int nbulk,
-                                const Tile* edge, int nedge, const WallLine* lines, int nlines, R* wterm,
-                                hipStream_t s) {
+                                const Tile* edge, int nedge, R* side, int from, hipStream_t s) {
     constexpr dim3 blk(TX, 256 / TX);
-    if (nlines > 0) wall_prep_kernel<R><<<(nlines + 255) / 256, 256, 0, s>>>(src, doms, lines, nlines, wterm);
-    if (nbulk > 0) step_kernel<R, TX, RPT, false><<<nbulk, blk, 0, s>>>(src, dst, doms, bulk, nbulk, wterm);
-    if (nedge > 0) step_kernel<R, TX, RPT, true><<<nedge, blk, 0, s>>>(src, dst, doms, edge, nedge, wterm);
+    if (nbulk > 0) step_kernel<R, TX, RPT, false><<<nbulk, blk, 0, s>>>(src, dst, doms, bulk, nbulk, side, from);
+    if (nedge > 0) step_kernel<R, TX, RPT, true><<<nedge, blk, 0, s>>>(src, dst, doms, edge, nedge, side, from);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_step(int tile_x, int tile_y, const R* src, R* dst, const Dom<R>* doms, const Tile* bulk,
-                       int nbulk, const Tile* edge, int nedge, const WallLine* lines, int nlines, R* wterm,
-                       hipStream_t s) {
-#define LBM13_STEP_ARGS src, dst, doms, bulk, nbulk, edge, nedge, lines, nlines, wterm, s
+                       int nbulk, const Tile* edge, int nedge, R* side, int from, hipStream_t s) {
+#define LBM13_STEP_ARGS src, dst, doms, bulk, nbulk, edge, nedge, side, from, s
     if (tile_x == 64 && tile_y == 4) return launch_step_t<R, 64, 1>(LBM13_STEP_ARGS);
     if (tile_x == 64 && tile_y == 8) return launch_step_t<R, 64, 2>(LBM13_STEP_ARGS);
     if (tile_x == 64 && tile_y == 16) return launch_step_t<R, 64, 4>(LBM13_STEP_ARGS);
@@ -634,6 +745,13 @@ hipError_t launch_diag(int tile_x, int tile_y, const R* src, const Dom<R>* doms,
         }
     }
     diag_final_kernel<R><<<ndom, 256, 0, s>>>(doms, part, out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_side_fill(const R* src, const Dom<R>* doms, const WallLine* lines, int nlines, R* side, int buf,
+                            hipStream_t s) {
+    if (nlines > 0) side_fill_kernel<R><<<(nlines + 255) / 256, 256, 0, s>>>(src, doms, lines, nlines, side, buf);
     return hipGetLastError();
 }
 
@@ -669,7 +787,8 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
 
 #define LBM13_INSTANTIATE(R)                                                                                      \
     template hipError_t launch_step<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, \
-                                       const WallLine*, int, R*, hipStream_t);                                    \
+                                       R*, int, hipStream_t);                                                     \
+    template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, hipStream_t); \
     template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*,         \
                                        double*, hipStream_t);                                                     \
     template hipError_t launch_init<R>(int, int, R*, const Dom<R>*, int, const double*, const double*,           \
