@@ -27,7 +27,7 @@ template <typename R>
 hipError_t launch_step(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, R*, int,
                        hipStream_t);
 template <typename R>
-hipError_t launch_side_fill(const R*, const Dom<R>*, const WallLine*, int, R*, int, hipStream_t);
+hipError_t launch_side_fill(const R*, const Dom<R>*, const WallLine*, int, R*, int, int, hipStream_t);
 template <typename R>
 hipError_t launch_diag(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, double*, hipStream_t);
 template <typename R>
@@ -376,15 +376,16 @@ hipError_t launch_one_step(lbm13_batch* b, int from, hipStream_t s) {
 
 // Wall-layer side values of the kept state (after init, set_state, load).
 template <typename R>
-hipError_t fill_side(lbm13_batch* b) {
+hipError_t fill_side(lbm13_batch* b, int only_dom) {
     const WallLine* lines = reinterpret_cast<const WallLine*>(b->ws + b->L.lines);
     R* side = reinterpret_cast<R*>(b->ws + b->L.wall);
     return lbm13::launch_side_fill<R>(buf<R>(b, b->cur), doms_dev<R>(b), lines, (int)b->lines.size(), side, b->cur,
-                                      b->stream);
+                                      only_dom, b->stream);
 }
 
-hipError_t fill_side_any(lbm13_batch* b) {
-    return b->precision == LBM13_FP64 ? fill_side<double>(b) : fill_side<float>(b);
+// only_dom = -1: every domain.
+hipError_t fill_side_any(lbm13_batch* b, int only_dom) {
+    return b->precision == LBM13_FP64 ? fill_side<double>(b, only_dom) : fill_side<float>(b, only_dom);
 }
 
 template <typename R>
@@ -573,7 +574,7 @@ int lbm13_batch_set_params(lbm13_batch* b, int i, const lbm13_params* p, const l
     bool any_state = false;
     for (char h : b->has_state) any_state = any_state || h;
     if (any_state) {
-        e = fill_side_any(b);  // walls may have changed under a kept state
+        e = fill_side_any(b, -1);  // walls may have changed under a kept state
         if (e != hipSuccess) return hip_fail(b, e, "side fill launch");
     }
     return LBM13_OK;
@@ -592,7 +593,7 @@ int lbm13_batch_init_moments(lbm13_batch* b, int i, const double* rho, const dou
         e = lbm13::launch_init<float>(b->nx[i], b->ny[i], buf<float>(b, b->cur), doms_dev<float>(b), i, rho, ux, uy, T,
                                       coef, b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "init launch");
-    e = fill_side_any(b);
+    e = fill_side_any(b, i);
     if (e != hipSuccess) return hip_fail(b, e, "side fill launch");
     b->has_state[i] = 1;
     b->steps = 0;
@@ -669,7 +670,7 @@ int lbm13_batch_set_state(lbm13_batch* b, int i, const double* src) {
         e = lbm13::launch_set_state<float>(b->nx[i], b->ny[i], buf<float>(b, b->cur), doms_dev<float>(b), i, src,
                                            b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "set_state launch");
-    e = fill_side_any(b);
+    e = fill_side_any(b, i);
     if (e != hipSuccess) return hip_fail(b, e, "side fill launch");
     b->has_state[i] = 1;
     return LBM13_OK;
@@ -710,7 +711,7 @@ int lbm13_batch_load(lbm13_batch* b, int i, const void* src) {
     if (!b->has_params[i]) return fail(b, LBM13_ESTATE, "set_params first");
     int st = raw_copy(b, i, nullptr, src);
     if (st != LBM13_OK) return st;
-    hipError_t e = fill_side_any(b);
+    hipError_t e = fill_side_any(b, i);
     if (e != hipSuccess) return hip_fail(b, e, "side fill launch");
     b->has_state[i] = 1;
     return LBM13_OK;

@@ -186,10 +186,11 @@ __device__ __forceinline__ R* side_line(R* side, const Dom<R>& D, int buf, int l
 template <typename R>
 __global__ __launch_bounds__(256) void side_fill_kernel(const R* __restrict__ src, const Dom<R>* __restrict__ doms,
                                                         const WallLine* __restrict__ lines, int nlines,
-                                                        R* __restrict__ side, int buf) {
+                                                        R* __restrict__ side, int buf, int only_dom) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nlines) return;
     const WallLine wl = lines[l];
+    if (only_dom >= 0 && wl.dom != only_dom) return;
     const Dom<R>& D = doms[wl.dom];
     const R* __restrict__ b = src + D.off;
     const int w = wl.w, pos = wl.pos;
@@ -421,13 +422,11 @@ __global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R*
         const int y = tl.y0 + threadIdx.y + r * TYB;
         if (x >= D.nx || y >= D.ny) continue;
         R g[13];
-        if (WALLS) {
-            const bool near = (!D.xper && (x < 2 || x >= D.nx - 2)) || (!D.yper && (y < 2 || y >= D.ny - 2));
-            if (near) gather_wall(a, side, D, from, x, y, g);
-            else gather_bulk(a, D, x, y, g);
-        } else {
-            gather_bulk(a, D, x, y, g);
-        }
+        // In tiles that touch a wall every node takes the clamped gather with
+        // per-wall fix-ups (identical to the bulk gather away from walls), so a
+        // wavefront never runs both gathers.
+        if (WALLS) gather_wall(a, side, D, from, x, y, g);
+        else gather_bulk(a, D, x, y, g);
         if (D.collide) collide(g, D);
         store_node(o, D.plane, y * D.pitch + x, g);
         if (WALLS) record_wall_layers(side, D, 1 - from, x, y, g);
@@ -750,8 +749,9 @@ hipError_t launch_diag(int tile_x, int tile_y, const R* src, const Dom<R>* doms,
 
 template <typename R>
 hipError_t launch_side_fill(const R* src, const Dom<R>* doms, const WallLine* lines, int nlines, R* side, int buf,
-                            hipStream_t s) {
-    if (nlines > 0) side_fill_kernel<R><<<(nlines + 255) / 256, 256, 0, s>>>(src, doms, lines, nlines, side, buf);
+                            int only_dom, hipStream_t s) {
+    if (nlines > 0)
+        side_fill_kernel<R><<<(nlines + 255) / 256, 256, 0, s>>>(src, doms, lines, nlines, side, buf, only_dom);
     return hipGetLastError();
 }
 
@@ -788,7 +788,8 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
 #define LBM13_INSTANTIATE(R)                                                                                      \
     template hipError_t launch_step<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, \
                                        R*, int, hipStream_t);                                                     \
-    template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, hipStream_t); \
+    template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, int,          \
+                                            hipStream_t);                                                         \
     template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*,         \
                                        double*, hipStream_t);                                                     \
     template hipError_t launch_init<R>(int, int, R*, const Dom<R>*, int, const double*, const double*,           \
