@@ -182,6 +182,13 @@ int lbm13_autotune(lbm13_ctx *ctx, int steps, int *tile_x, int *tile_y);
  * replays for every full block of k steps; k = 0 switches graphs off. */
 int lbm13_use_graph(lbm13_ctx *ctx, int k);
 
+/* Time steps advanced per kernel launch: 1, or 2 (each workgroup advances its
+ * tile and a two-node halo by one step into LDS, then the tile by a second
+ * step; same arithmetic per node, so results equal two single steps, with
+ * about half the HBM traffic per step).  An odd remainder of lbm13_step(n) is
+ * done by a single-step launch.  EINVAL for other values. */
+int lbm13_set_steps_per_launch(lbm13_ctx *ctx, int k);
+
 /* Destroy the context (frees host objects and graphs; never the workspace). */
 int lbm13_destroy(lbm13_ctx *ctx);
 
@@ -215,6 +222,7 @@ int lbm13_batch_load(lbm13_batch *b, int i, const void *src);
 int lbm13_batch_set_tile(lbm13_batch *b, int tile_x, int tile_y);
 int lbm13_batch_autotune(lbm13_batch *b, int steps, int *tile_x, int *tile_y);
 int lbm13_batch_use_graph(lbm13_batch *b, int k);
+int lbm13_batch_set_steps_per_launch(lbm13_batch *b, int k);
 long long lbm13_batch_nodes(const lbm13_batch *b);
 int lbm13_batch_destroy(lbm13_batch *b);
 const char *lbm13_batch_last_error(const lbm13_batch *b);

@@ -29,6 +29,8 @@ hipError_t launch_step(int, int, const R*, R*, const Dom<R>*, const Tile*, int, 
 template <typename R>
 hipError_t launch_side_fill(const R*, const Dom<R>*, const WallLine*, int, R*, int, int, hipStream_t);
 template <typename R>
+hipError_t launch_step2(const R*, R*, const Dom<R>*, const Tile*, int, R*, int, hipStream_t);
+template <typename R>
 hipError_t launch_diag(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, double*, hipStream_t);
 template <typename R>
 hipError_t launch_init(int, int, R*, const Dom<R>*, int, const double*, const double*, const double*, const double*,
@@ -60,9 +62,9 @@ bool valid_shape(int tx, int ty) {
 }
 
 struct Layout {
-    size_t doms, coef, tiles_all, tiles_run, part, diag, lines, wall, bufA, bufB, total;
+    size_t doms, coef, tiles_all, tiles_run, tiles_fused, part, diag, lines, wall, bufA, bufB, total;
     size_t buf_bytes;
-    int tmax;
+    int tmax, tfmax;
     long long nlines_max;
     std::vector<long long> off;   // per-domain element offset of the populations
     std::vector<long long> woff;  // per-domain element offset of the wall-layer side array
@@ -78,7 +80,9 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
     L.woff.resize(count);
     L.pitch.resize(count);
     L.plane.resize(count);
-    long long tmax = 0, lines = 0;
+    long long tmax = 0, tfmax = 0, lines = 0;
+    const int ftw = precision == LBM13_FP64 ? lbm13::Fused<double>::TW : lbm13::Fused<float>::TW;
+    const int fth = precision == LBM13_FP64 ? lbm13::Fused<double>::TH : lbm13::Fused<float>::TH;
     size_t elems = 0;
     for (int d = 0; d < count; ++d) {
         if (nx[d] < 2 || ny[d] < 2 || nx[d] > (1 << 16) || ny[d] > (1 << 16)) return false;
@@ -95,14 +99,17 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
         for (auto& s : kShapes)
             t = std::max(t, (long long)((nx[d] + s[0] - 1) / s[0]) * ((ny[d] + s[1] - 1) / s[1]));
         tmax += t;
+        tfmax += (long long)((nx[d] + ftw - 1) / ftw) * ((ny[d] + fth - 1) / fth);
     }
-    if (tmax >= INT32_MAX / 2) return false;
+    if (tmax >= INT32_MAX / 2 || tfmax >= INT32_MAX / 2) return false;
     L.tmax = (int)tmax;
+    L.tfmax = (int)tfmax;
     size_t p = 0;
     L.doms = p;      p = align_up(p + dom_size * count, kAlign);
     L.coef = p;      p = align_up(p + sizeof(double) * kCoef * count, kAlign);
     L.tiles_all = p; p = align_up(p + sizeof(Tile) * tmax, kAlign);
     L.tiles_run = p; p = align_up(p + sizeof(Tile) * tmax, kAlign);
+    L.tiles_fused = p; p = align_up(p + sizeof(Tile) * tfmax, kAlign);
     L.part = p;      p = align_up(p + sizeof(double) * lbm13::kDiagPartials * tmax, kAlign);
     L.diag = p;      p = align_up(p + sizeof(double) * lbm13::kDiagOut * count, kAlign);
     L.nlines_max = lines;
@@ -170,8 +177,9 @@ struct lbm13_batch {
     std::vector<double> coef_host;
     std::vector<int> sides_kind;          // 4 per domain
     std::vector<char> has_params, has_state;
-    std::vector<Tile> all, run;
+    std::vector<Tile> all, run, fused;
     std::vector<WallLine> lines;
+    int spl = 1;                          // time steps per launch (1 or 2)
     int nbulk = 0, nedge = 0;
     int tile_x = 64, tile_y = 8;
     int cur = 0;                          // buffer holding the current state
@@ -264,6 +272,15 @@ int rebuild(lbm13_batch* b) {
     if ((int)b->all.size() > b->L.tmax) return fail(b, LBM13_EINVAL, "tile table overflow");
     b->run = bulk;
     b->run.insert(b->run.end(), edge.begin(), edge.end());
+    b->fused.clear();
+    {
+        const int ftw = b->precision == LBM13_FP64 ? lbm13::Fused<double>::TW : lbm13::Fused<float>::TW;
+        const int fth = b->precision == LBM13_FP64 ? lbm13::Fused<double>::TH : lbm13::Fused<float>::TH;
+        for (int d = 0; d < b->count; ++d)
+            for (int y0 = 0; y0 < b->ny[d]; y0 += fth)
+                for (int x0 = 0; x0 < b->nx[d]; x0 += ftw) b->fused.push_back(Tile{d, x0, y0, 0});
+        if ((int)b->fused.size() > b->L.tfmax) return fail(b, LBM13_EINVAL, "fused tile table overflow");
+    }
     b->lines.clear();
     for (int d = 0; d < b->count; ++d) {
         const int* k = &b->sides_kind[4 * d];
@@ -291,6 +308,9 @@ int rebuild(lbm13_batch* b) {
     e = hipMemcpyAsync(b->ws + b->L.tiles_run, b->run.data(), sizeof(Tile) * b->run.size(), hipMemcpyHostToDevice,
                        b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "upload tile table");
+    e = hipMemcpyAsync(b->ws + b->L.tiles_fused, b->fused.data(), sizeof(Tile) * b->fused.size(),
+                       hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "upload fused tile table");
     if (!b->lines.empty()) {
         e = hipMemcpyAsync(b->ws + b->L.lines, b->lines.data(), sizeof(WallLine) * b->lines.size(),
                            hipMemcpyHostToDevice, b->stream);
@@ -374,6 +394,14 @@ hipError_t launch_one_step(lbm13_batch* b, int from, hipStream_t s) {
                                  b->nbulk, run + b->nbulk, b->nedge, side, from, s);
 }
 
+template <typename R>
+hipError_t launch_two_steps(lbm13_batch* b, int from, hipStream_t s) {
+    const Tile* tiles = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_fused);
+    R* side = reinterpret_cast<R*>(b->ws + b->L.wall);
+    return lbm13::launch_step2<R>(buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), tiles, (int)b->fused.size(),
+                                  side, from, s);
+}
+
 // Wall-layer side values of the kept state (after init, set_state, load).
 template <typename R>
 hipError_t fill_side(lbm13_batch* b, int only_dom) {
@@ -406,8 +434,9 @@ int capture_graph(lbm13_batch* b, int parity) {
     if (e != hipSuccess) return hip_fail(b, e, "begin capture");
     int from = parity;
     hipError_t le = hipSuccess;
-    for (int s = 0; s < b->graph_k && le == hipSuccess; ++s) {
-        le = launch_one_step<R>(b, from, b->capture_stream);
+    for (int s = 0; s < b->graph_k && le == hipSuccess; s += b->spl) {
+        le = b->spl == 2 ? launch_two_steps<R>(b, from, b->capture_stream)
+                         : launch_one_step<R>(b, from, b->capture_stream);
         from = 1 - from;
     }
     hipGraph_t g = nullptr;
@@ -439,6 +468,13 @@ int step_impl(lbm13_batch* b, long long n) {
         if (e != hipSuccess) return hip_fail(b, e, "graph launch");
         n -= b->graph_k;
         b->steps += b->graph_k;
+    }
+    while (b->spl == 2 && n >= 2) {
+        hipError_t e = launch_two_steps<R>(b, b->cur, b->stream);
+        if (e != hipSuccess) return hip_fail(b, e, "two-step launch");
+        b->cur = 1 - b->cur;
+        b->steps += 2;
+        n -= 2;
     }
     for (long long s = 0; s < n; ++s) {
         int st = do_step<R>(b, b->cur);
@@ -741,6 +777,14 @@ int lbm13_batch_use_graph(lbm13_batch* b, int k) {
     return LBM13_OK;
 }
 
+int lbm13_batch_set_steps_per_launch(lbm13_batch* b, int k) {
+    if (!b) return LBM13_EINVAL;
+    if (k != 1 && k != 2) return fail(b, LBM13_EINVAL, "steps per launch must be 1 or 2");
+    drop_graphs(b);
+    b->spl = k;
+    return LBM13_OK;
+}
+
 long long lbm13_batch_nodes(const lbm13_batch* b) {
     if (!b) return 0;
     long long n = 0;
@@ -818,6 +862,10 @@ int lbm13_autotune(lbm13_ctx* c, int steps, int* tile_x, int* tile_y) {
 }
 
 int lbm13_use_graph(lbm13_ctx* c, int k) { return c ? lbm13_batch_use_graph(c->b, k) : LBM13_EINVAL; }
+
+int lbm13_set_steps_per_launch(lbm13_ctx* c, int k) {
+    return c ? lbm13_batch_set_steps_per_launch(c->b, k) : LBM13_EINVAL;
+}
 
 int lbm13_destroy(lbm13_ctx* c) {
     if (!c) return LBM13_EINVAL;

@@ -60,6 +60,19 @@ struct alignas(16) WallLine {
     int dom, w, pos, line;
 };
 
+// Tile of the two-steps-per-launch kernel: the region (TW + 4) x (TH + 4) x 13
+// populations must fit the 64 KB of LDS a workgroup can address.
+template <typename R>
+struct Fused;
+template <>
+struct Fused<float> {
+    static constexpr int TW = 64, TH = 12;
+};
+template <>
+struct Fused<double> {
+    static constexpr int TW = 32, TH = 8;
+};
+
 constexpr int kDiagPartials = 10;  // per-tile partial reductions
 constexpr int kDiagOut = 16;       // values per domain
 

@@ -280,82 +280,123 @@ __device__ __forceinline__ R wall_term(const WallState<R>& ws, bool abb) {
                    R(kM[7][I]) * ws.odd[3] + R(kM[8][I]) * ws.odd[4] + R(kM[9][I]) * ws.odd[5]);
 }
 
+// Population sources for the gathers.  Coordinates passed to cx/cy are a
+// node's coordinate minus a velocity; cx/cy return an in-bounds coordinate:
+// wrapped on a periodic axis, clamped on a walled axis (a clamped link is
+// always replaced by a wall fix-up).
+//   GlobalSrc: the stored state in HBM (domain coordinates).
+//   LdsSrc: a tile's region (tile plus two nodes on each side) in LDS, indexed
+//   by unwrapped domain coordinates relative to the region's origin.
+template <typename R>
+struct GlobalSrc {
+    const R* __restrict__ b;
+    int S, P, nx, ny, xper, yper;
+    __device__ __forceinline__ int cx(int X) const { return xper ? wrap(X, nx) : min(max(X, 0), nx - 1); }
+    __device__ __forceinline__ int cy(int Y) const { return yper ? wrap(Y, ny) : min(max(Y, 0), ny - 1); }
+    __device__ __forceinline__ R get(int i, int X, int Y) const { return b[i * S + Y * P + X]; }
+};
+
+template <typename R, int RW, int RH>
+struct LdsSrc {
+    const R* l;
+    int ox, oy, nx, ny, xper, yper;
+    __device__ __forceinline__ int cx(int X) const { return xper ? X : min(max(X, 0), nx - 1); }
+    __device__ __forceinline__ int cy(int Y) const { return yper ? Y : min(max(Y, 0), ny - 1); }
+    __device__ __forceinline__ R get(int i, int X, int Y) const { return l[(i * RH + (Y - oy)) * RW + (X - ox)]; }
+};
+
+// Side values (rho' and E' of the first wall layer, rho' of the second) of the
+// line at position pos of wall w: from the global side array, or from the
+// copy a fused launch keeps in LDS for its region.
+template <typename R>
+struct GlobalSide {
+    R* side;
+    int buf;
+    __device__ __forceinline__ void get(const Dom<R>& D, int w, int pos, R& r0, R& e0, R& r1) const {
+        const int line = w == 0 ? pos : w == 1 ? D.ny + pos : w == 2 ? 2 * D.ny + pos : 2 * D.ny + D.nx + pos;
+        const R* p = side_line(side, D, buf, line);
+        r0 = p[0];
+        e0 = p[1];
+        r1 = p[2];
+    }
+};
+
+template <typename R, int RW, int RH>
+struct LdsSide {
+    const R* xs;  // [2][RH][3]: West, East walls by region row
+    const R* ys;  // [2][RW][3]: South, North walls by region column
+    int ox, oy;
+    __device__ __forceinline__ void get(const Dom<R>& D, int w, int pos, R& r0, R& e0, R& r1) const {
+        const R* p = w < 2 ? xs + (w * RH + (pos - oy)) * 3 : ys + ((w - 2) * RW + (pos - ox)) * 3;
+        r0 = p[0];
+        e0 = p[1];
+        r1 = p[2];
+    }
+};
+
 // Replace link I, whose source lies beyond wall w, by its reversed path from x'
 // (tangential coordinate kept, normal coordinate reflected through the wall).
-template <int I, typename R>
-__device__ __forceinline__ void fix_link(const R* __restrict__ b, const Dom<R>& D, int w, int x, int y,
+template <int I, typename R, typename Src>
+__device__ __forceinline__ void fix_link(const Src& A, const Dom<R>& D, int w, int x, int y,
                                          const WallState<R>& ws, R g[13]) {
     int px = x, py = y;
     if (w == 0) px = -1 + kVX[I] - x;
     else if (w == 1) px = 2 * D.nx - 1 + kVX[I] - x;
     else if (w == 2) py = -1 + kVY[I] - y;
     else py = 2 * D.ny - 1 + kVY[I] - y;
-    const R src = b[kOPP[I] * D.plane + py * D.pitch + px];
+    const R src = A.get(kOPP[I], px, py);
     const bool normal = (w < 2) ? (kVY[I] == 0) : (kVX[I] == 0);
     const bool abb = normal && D.kind[w] == kDirichletT;
     g[I] = (abb ? -src : src) + wall_term<I>(ws, abb);
 }
 
 // Gather for a node within two nodes of a wall: every link is first read with
-// clamped (in-bounds) coordinates, then the links whose source lies beyond a
-// wall are replaced (bounce-back for links with a tangential component and for
-// every link at an adiabatic wall, anti-bounce-back for links normal to a
-// temperature wall; sec. 7).  y walls are applied first and x walls last, so a
-// diagonal source beyond two walls takes the West/East wall.
-template <typename R>
-__device__ __forceinline__ void gather_wall(const R* __restrict__ b, const R* __restrict__ side, const Dom<R>& D,
-                                            int buf, int x, int y, R g[13]) {
-    const int P = D.pitch, S = D.plane;
-    int xm1 = x - 1, xm2 = x - 2, xp1 = x + 1, xp2 = x + 2;
-    int ym1 = y - 1, ym2 = y - 2, yp1 = y + 1, yp2 = y + 2;
-    if (D.xper) {
-        xm1 = wrap(xm1, D.nx); xm2 = wrap(xm2, D.nx); xp1 = wrap(xp1, D.nx); xp2 = wrap(xp2, D.nx);
-    } else {
-        xm1 = max(xm1, 0); xm2 = max(xm2, 0); xp1 = min(xp1, D.nx - 1); xp2 = min(xp2, D.nx - 1);
-    }
-    if (D.yper) {
-        ym1 = wrap(ym1, D.ny); ym2 = wrap(ym2, D.ny); yp1 = wrap(yp1, D.ny); yp2 = wrap(yp2, D.ny);
-    } else {
-        ym1 = max(ym1, 0); ym2 = max(ym2, 0); yp1 = min(yp1, D.ny - 1); yp2 = min(yp2, D.ny - 1);
-    }
-    const int r0 = y * P, rm1 = ym1 * P, rm2 = ym2 * P, rp1 = yp1 * P, rp2 = yp2 * P;
-    g[0] = b[r0 + x];
-    g[1] = b[1 * S + r0 + xm1];
-    g[2] = b[2 * S + rm1 + x];
-    g[3] = b[3 * S + r0 + xp1];
-    g[4] = b[4 * S + rp1 + x];
-    g[5] = b[5 * S + rm1 + xm1];
-    g[6] = b[6 * S + rm1 + xp1];
-    g[7] = b[7 * S + rp1 + xp1];
-    g[8] = b[8 * S + rp1 + xm1];
-    g[9] = b[9 * S + r0 + xm2];
-    g[10] = b[10 * S + rm2 + x];
-    g[11] = b[11 * S + r0 + xp2];
-    g[12] = b[12 * S + rp2 + x];
-    R* sd = const_cast<R*>(side);
+// in-bounds coordinates, then the links whose source lies beyond a wall are
+// replaced (bounce-back for links with a tangential component and for every
+// link at an adiabatic wall, anti-bounce-back for links normal to a temperature
+// wall; sec. 7).  y walls are applied first and x walls last, so a diagonal
+// source beyond two walls takes the West/East wall.
+template <typename R, typename Src, typename Side>
+__device__ __forceinline__ void gather_wall(const Src& A, const Side& SD, const Dom<R>& D, int x, int y, R g[13]) {
+    const int xm1 = A.cx(x - 1), xm2 = A.cx(x - 2), xp1 = A.cx(x + 1), xp2 = A.cx(x + 2);
+    const int ym1 = A.cy(y - 1), ym2 = A.cy(y - 2), yp1 = A.cy(y + 1), yp2 = A.cy(y + 2);
+    g[0] = A.get(0, x, y);
+    g[1] = A.get(1, xm1, y);
+    g[2] = A.get(2, x, ym1);
+    g[3] = A.get(3, xp1, y);
+    g[4] = A.get(4, x, yp1);
+    g[5] = A.get(5, xm1, ym1);
+    g[6] = A.get(6, xp1, ym1);
+    g[7] = A.get(7, xp1, yp1);
+    g[8] = A.get(8, xm1, yp1);
+    g[9] = A.get(9, xm2, y);
+    g[10] = A.get(10, x, ym2);
+    g[11] = A.get(11, xp2, y);
+    g[12] = A.get(12, x, yp2);
+    R r0, e0, r1;
     if (!D.yper && y < 2) {  // South wall: links with v_y > 0
-        const R* p = side_line(sd, D, buf, 2 * D.ny + x);
-        const WallState<R> ws = wall_state(D, 2, p[0], p[1], p[2]);
-        if (y == 0) { fix_link<2>(b, D, 2, x, y, ws, g); fix_link<5>(b, D, 2, x, y, ws, g); fix_link<6>(b, D, 2, x, y, ws, g); }
-        fix_link<10>(b, D, 2, x, y, ws, g);
+        SD.get(D, 2, x, r0, e0, r1);
+        const WallState<R> ws = wall_state(D, 2, r0, e0, r1);
+        if (y == 0) { fix_link<2>(A, D, 2, x, y, ws, g); fix_link<5>(A, D, 2, x, y, ws, g); fix_link<6>(A, D, 2, x, y, ws, g); }
+        fix_link<10>(A, D, 2, x, y, ws, g);
     }
     if (!D.yper && y >= D.ny - 2) {  // North wall: links with v_y < 0
-        const R* p = side_line(sd, D, buf, 2 * D.ny + D.nx + x);
-        const WallState<R> ws = wall_state(D, 3, p[0], p[1], p[2]);
-        if (y == D.ny - 1) { fix_link<4>(b, D, 3, x, y, ws, g); fix_link<7>(b, D, 3, x, y, ws, g); fix_link<8>(b, D, 3, x, y, ws, g); }
-        fix_link<12>(b, D, 3, x, y, ws, g);
+        SD.get(D, 3, x, r0, e0, r1);
+        const WallState<R> ws = wall_state(D, 3, r0, e0, r1);
+        if (y == D.ny - 1) { fix_link<4>(A, D, 3, x, y, ws, g); fix_link<7>(A, D, 3, x, y, ws, g); fix_link<8>(A, D, 3, x, y, ws, g); }
+        fix_link<12>(A, D, 3, x, y, ws, g);
     }
     if (!D.xper && x < 2) {  // West wall: links with v_x > 0
-        const R* p = side_line(sd, D, buf, y);
-        const WallState<R> ws = wall_state(D, 0, p[0], p[1], p[2]);
-        if (x == 0) { fix_link<1>(b, D, 0, x, y, ws, g); fix_link<5>(b, D, 0, x, y, ws, g); fix_link<8>(b, D, 0, x, y, ws, g); }
-        fix_link<9>(b, D, 0, x, y, ws, g);
+        SD.get(D, 0, y, r0, e0, r1);
+        const WallState<R> ws = wall_state(D, 0, r0, e0, r1);
+        if (x == 0) { fix_link<1>(A, D, 0, x, y, ws, g); fix_link<5>(A, D, 0, x, y, ws, g); fix_link<8>(A, D, 0, x, y, ws, g); }
+        fix_link<9>(A, D, 0, x, y, ws, g);
     }
     if (!D.xper && x >= D.nx - 2) {  // East wall: links with v_x < 0
-        const R* p = side_line(sd, D, buf, D.ny + y);
-        const WallState<R> ws = wall_state(D, 1, p[0], p[1], p[2]);
-        if (x == D.nx - 1) { fix_link<3>(b, D, 1, x, y, ws, g); fix_link<6>(b, D, 1, x, y, ws, g); fix_link<7>(b, D, 1, x, y, ws, g); }
-        fix_link<11>(b, D, 1, x, y, ws, g);
+        SD.get(D, 1, y, r0, e0, r1);
+        const WallState<R> ws = wall_state(D, 1, r0, e0, r1);
+        if (x == D.nx - 1) { fix_link<3>(A, D, 1, x, y, ws, g); fix_link<6>(A, D, 1, x, y, ws, g); fix_link<7>(A, D, 1, x, y, ws, g); }
+        fix_link<11>(A, D, 1, x, y, ws, g);
     }
 }
 
@@ -425,11 +466,107 @@ __global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R*
         // In tiles that touch a wall every node takes the clamped gather with
         // per-wall fix-ups (identical to the bulk gather away from walls), so a
         // wavefront never runs both gathers.
-        if (WALLS) gather_wall(a, side, D, from, x, y, g);
-        else gather_bulk(a, D, x, y, g);
+        if (WALLS) {
+            const GlobalSrc<R> A{a, D.plane, D.pitch, D.nx, D.ny, D.xper, D.yper};
+            gather_wall(A, GlobalSide<R>{side, from}, D, x, y, g);
+        } else {
+            gather_bulk(a, D, x, y, g);
+        }
         if (D.collide) collide(g, D);
         store_node(o, D.plane, y * D.pitch + x, g);
         if (WALLS) record_wall_layers(side, D, 1 - from, x, y, g);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per launch.  A workgroup owns a TW x TH tile.  Phase 1 advances
+// the tile and a two-node halo around it (the reach of the 13 velocities) from
+// t to t + 1, gathering from HBM, and keeps the post-collision result in LDS;
+// phase 2 advances the tile from t + 1 to t + 2 gathering from LDS and writes
+// HBM once.  Each node's arithmetic is the single-step kernel's, so the result
+// equals two single steps; HBM traffic per step is about halved (the halo is
+// re-read from L2 by neighbouring tiles), for (TW+4)(TH+4)/(TW TH) times the
+// phase-1 collision work.  Wall-layer densities of step t + 1 are kept in LDS
+// for phase 2's wall states.
+__device__ __forceinline__ int pmod(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <typename R, int TW, int TH>
+__global__ __launch_bounds__(256) void step2_kernel(const R* __restrict__ src, R* __restrict__ dst,
+                                                    const Dom<R>* __restrict__ doms,
+                                                    const Tile* __restrict__ tiles, int ntiles,
+                                                    R* __restrict__ side, int from) {
+    constexpr int NT = 256, RW = TW + 4, RH = TH + 4;
+    __shared__ R lds[13 * RH * RW];
+    __shared__ R xs[2 * RH * 3];
+    __shared__ R ys[2 * RW * 3];
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const Tile tl = tiles[t];
+    const Dom<R>& D = doms[tl.dom];
+    const R* __restrict__ a = src + D.off;
+    R* __restrict__ o = dst + D.off;
+    const int ox = tl.x0 - 2, oy = tl.y0 - 2;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+
+    const GlobalSrc<R> G{a, D.plane, D.pitch, D.nx, D.ny, D.xper, D.yper};
+    const GlobalSide<R> GS{side, from};
+    for (int r = tid; r < RW * RH; r += NT) {
+        const int lx = r % RW, ly = r / RW;
+        int X = ox + lx, Y = oy + ly;
+        if (D.xper) X = pmod(X, D.nx);
+        else if (X < 0 || X >= D.nx) continue;
+        if (D.yper) Y = pmod(Y, D.ny);
+        else if (Y < 0 || Y >= D.ny) continue;
+        R g[13];
+        const bool xw = !D.xper && (X < 2 || X >= D.nx - 2);
+        const bool yw = !D.yper && (Y < 2 || Y >= D.ny - 2);
+        if (xw || yw) gather_wall(G, GS, D, X, Y, g);
+        else gather_bulk(a, D, X, Y, g);
+        if (D.collide) collide(g, D);
+#pragma unroll
+        for (int i = 0; i < 13; ++i) lds[(i * RH + ly) * RW + lx] = g[i];
+        if (xw || yw) {
+            R rho = R(0), E = R(0);
+#pragma unroll
+            for (int i = 0; i < 13; ++i) {
+                rho += g[i];
+                E += R(c_M[1][i]) * g[i];
+            }
+            if (xw) {
+                if (X == 0) { xs[(0 * RH + ly) * 3 + 0] = rho; xs[(0 * RH + ly) * 3 + 1] = E; }
+                if (X == 1) xs[(0 * RH + ly) * 3 + 2] = rho;
+                if (X == D.nx - 1) { xs[(1 * RH + ly) * 3 + 0] = rho; xs[(1 * RH + ly) * 3 + 1] = E; }
+                if (X == D.nx - 2) xs[(1 * RH + ly) * 3 + 2] = rho;
+            }
+            if (yw) {
+                if (Y == 0) { ys[(0 * RW + lx) * 3 + 0] = rho; ys[(0 * RW + lx) * 3 + 1] = E; }
+                if (Y == 1) ys[(0 * RW + lx) * 3 + 2] = rho;
+                if (Y == D.ny - 1) { ys[(1 * RW + lx) * 3 + 0] = rho; ys[(1 * RW + lx) * 3 + 1] = E; }
+                if (Y == D.ny - 2) ys[(1 * RW + lx) * 3 + 2] = rho;
+            }
+        }
+    }
+    __syncthreads();
+
+    const LdsSrc<R, RW, RH> L{lds, ox, oy, D.nx, D.ny, D.xper, D.yper};
+    const LdsSide<R, RW, RH> LS{xs, ys, ox, oy};
+    for (int r = tid; r < TW * TH; r += NT) {
+        const int lx = r % TW + 2, ly = r / TW + 2;
+        const int X = ox + lx, Y = oy + ly;
+        if (X >= D.nx || Y >= D.ny) continue;
+        R g[13];
+        const bool near = (!D.xper && (X < 2 || X >= D.nx - 2)) || (!D.yper && (Y < 2 || Y >= D.ny - 2));
+        if (near) {
+            gather_wall(L, LS, D, X, Y, g);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 13; ++i) g[i] = lds[(i * RH + ly - kVY[i]) * RW + lx - kVX[i]];
+        }
+        if (D.collide) collide(g, D);
+        store_node(o, D.plane, Y * D.pitch + X, g);
+        if (near) record_wall_layers(side, D, 1 - from, X, Y, g);
     }
 }
 
@@ -748,6 +885,15 @@ hipError_t launch_diag(int tile_x, int tile_y, const R* src, const Dom<R>* doms,
 }
 
 template <typename R>
+hipError_t launch_step2(const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int ntiles, R* side, int from,
+                        hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    constexpr int TW = Fused<R>::TW, TH = Fused<R>::TH;
+    step2_kernel<R, TW, TH><<<ntiles, dim3(64, 4), 0, s>>>(src, dst, doms, tiles, ntiles, side, from);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_side_fill(const R* src, const Dom<R>* doms, const WallLine* lines, int nlines, R* side, int buf,
                             int only_dom, hipStream_t s) {
     if (nlines > 0)
@@ -788,6 +934,7 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
 #define LBM13_INSTANTIATE(R)                                                                                      \
     template hipError_t launch_step<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, \
                                        R*, int, hipStream_t);                                                     \
+    template hipError_t launch_step2<R>(const R*, R*, const Dom<R>*, const Tile*, int, R*, int, hipStream_t);       \
     template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, int,          \
                                             hipStream_t);                                                         \
     template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*,         \

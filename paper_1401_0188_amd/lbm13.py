@@ -93,6 +93,7 @@ def lib():
         "lbm13_set_tile": (i32, [vp, i32, i32]),
         "lbm13_autotune": (i32, [vp, i32, ip, ip]),
         "lbm13_use_graph": (i32, [vp, i32]),
+        "lbm13_set_steps_per_launch": (i32, [vp, i32]),
         "lbm13_destroy": (i32, [vp]),
         "lbm13_last_error": (ctypes.c_char_p, [vp]),
         "lbm13_batch_workspace_bytes": (sz, [i32, ip, ip, i32]),
@@ -110,6 +111,7 @@ def lib():
         "lbm13_batch_set_tile": (i32, [vp, i32, i32]),
         "lbm13_batch_autotune": (i32, [vp, i32, ip, ip]),
         "lbm13_batch_use_graph": (i32, [vp, i32]),
+        "lbm13_batch_set_steps_per_launch": (i32, [vp, i32]),
         "lbm13_batch_nodes": (i64, [vp]),
         "lbm13_batch_destroy": (i32, [vp]),
         "lbm13_batch_last_error": (ctypes.c_char_p, [vp]),
@@ -270,6 +272,9 @@ class Lattice(_Base):
     def use_graph(self, k: int):
         self._check(lib().lbm13_use_graph(self._h, int(k)))
 
+    def set_steps_per_launch(self, k: int):
+        self._check(lib().lbm13_set_steps_per_launch(self._h, int(k)))
+
     def destroy(self):
         if getattr(self, "_h", None):
             lib().lbm13_destroy(self._h)
@@ -375,6 +380,9 @@ class Batch(_Base):
 
     def use_graph(self, k: int):
         self._check(lib().lbm13_batch_use_graph(self._h, int(k)))
+
+    def set_steps_per_launch(self, k: int):
+        self._check(lib().lbm13_batch_set_steps_per_launch(self._h, int(k)))
 
     def nodes(self) -> int:
         return int(lib().lbm13_batch_nodes(self._h))

@@ -45,13 +45,17 @@ def params_pair(**kw):
 
 
 def run_both(nx, ny, fields, steps, kinds=(0, 0, 0, 0), u_t=(0, 0, 0, 0), T_w=(0, 0, 0, 0),
-             precision=0, tile=None, **kw):
+             precision=0, tile=None, spl=1, graph=0, **kw):
     lbm13 = _lb()
     po, pl = params_pair(**kw)
     so = oracle.sides(kinds, u_t, T_w)
     lat = lbm13.Lattice(nx, ny, precision)
     if tile:
         lat.set_tile(*tile)
+    if spl != 1:
+        lat.set_steps_per_launch(spl)
+    if graph:
+        lat.use_graph(graph)
     lat.set_params(sides=lbm13.make_sides(kinds, u_t, T_w), **pl)
     lat.init_moments(*fields)
     lat.step(steps)
@@ -435,3 +439,78 @@ def test_channel_profiles_match_startup_series():
         Tref = startup_conduction(xi, W, E0, dT, kappa, steps)
         heat = 13 * 0.71 * max(U, scale) ** 2
         assert np.abs(T - Tref).max() <= 0.03 * dT + heat, (kind, W, np.abs(T - Tref).max())
+
+
+# --------------------------------------------------------------------------- two steps per launch
+
+@pytest.mark.parametrize("name", sorted(WALL_CASES))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_two_steps_per_launch_walls(name, precision):
+    """Two time steps per launch (halo region in LDS) against the oracle,
+    including an odd remainder handled by a single-step launch."""
+    nx, ny, kinds, u_t, T_w, extra, steps = WALL_CASES[name]
+    steps = steps + 1
+    say("two-step %s precision %d, %d steps" % (name, precision, steps))
+    fields = workloads.cavity_fields(nx, ny=ny, seed=17, dT=0.01)
+    lat, gs, gm, fs, om, *_ = run_both(nx, ny, fields, steps, kinds, u_t, T_w, precision=precision, spl=2, **extra)
+    if precision == 0:
+        assert_fp64(gs, gm, fs, om)
+    else:
+        assert_fp32(gm, om)
+
+
+@pytest.mark.parametrize("shape", [(97, 53), (5, 3), (3, 70), (130, 2)])
+def test_two_steps_per_launch_periodic(shape):
+    nx, ny = shape
+    say("two-step periodic %s" % (shape,))
+    fields = workloads.shear_acoustic(nx, ny)
+    lat, gs, gm, fs, om, *_ = run_both(nx, ny, fields, 41, spl=2, graph=10, F0=(1e-5, -2e-5), g=(0.0, -1e-3))
+    assert_fp64(gs, gm, fs, om)
+
+
+def test_two_steps_per_launch_streaming_is_bit_exact():
+    lbm13 = _lb()
+    say("two-step collide-off")
+    nx, ny = 70, 35
+    rng = np.random.default_rng(3)
+    fields = (1 + 0.01 * rng.standard_normal((ny, nx)), 0.01 * rng.standard_normal((ny, nx)),
+              0.01 * rng.standard_normal((ny, nx)), -2 + 0.01 * rng.standard_normal((ny, nx)))
+    for kinds in ((1, 1, 1, 1), (0, 0, 1, 1), (0, 0, 0, 0)):
+        lat = lbm13.Lattice(nx, ny, lbm13.FP32_DEV)
+        lat.set_params(sides=lbm13.make_sides(kinds), collide=0)
+        lat.set_steps_per_launch(2)
+        lat.init_moments(*fields)
+        s0 = lat.get_state().cpu().numpy()
+        lat.step(24)
+        ref = oracle.run(s0, oracle.params(collide=0), oracle.sides(kinds), 24)
+        assert np.array_equal(lat.get_state().cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_two_steps_per_launch_full_size_4096(precision):
+    lbm13 = _lb()
+    say("two-step full size 4096^2 precision %d, 4 steps" % precision)
+    lat, gs, gm, fs, om, *_ = run_both(4096, 4096, workloads.shear_acoustic(4096), 4, precision=precision, spl=2)
+    if precision == 0:
+        assert_fp64(gs, gm, fs, om)
+    else:
+        assert_fp32(gm, om, tol=1e-6)
+
+
+@pytest.mark.parametrize("workload", ["cavities64", "channels128"])
+def test_two_steps_per_launch_batched_full_size(workload):
+    lbm13 = _lb()
+    import bench
+    specs = bench.cavity_specs() if workload == "cavities64" else bench.channel_specs()
+    steps = 200
+    say("two-step %s full batch, %d steps" % (workload, steps))
+    b = bench.build_batch(specs, lbm13.FP32_DEV)
+    b.set_steps_per_launch(2)
+    b.use_graph(50)
+    b.step(steps)
+    assert all(d["nonfinite"] == 0 for d in b.diagnostics())
+    order = sorted(range(len(specs)), key=lambda i: specs[i]["nx"] * specs[i]["ny"])[:3]
+    for i in order:
+        om = _oracle_for_spec(specs[i], steps)
+        gm = [t.cpu().numpy() for t in b.moments(i)]
+        assert_fp32(gm, om)
