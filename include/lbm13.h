@@ -75,7 +75,8 @@ typedef struct {
  * c_varpi_rho, c_varpi_E and the relaxation rates s_XX (also used for XY),
  * s_rx (also ry), s_eps, s_varpi, s_XXe.  Forces: F = F0 + g (rho - rho0) is
  * added to j after relaxation (F0: sec. 8 pressure gradient; g: sec. 5
- * buoyancy).  collide = 0 skips the collision (streaming and walls only). */
+ * buoyancy).  collide = 0 skips the collision (streaming and walls only).
+ * Q_E: uniform volumic energy source added to E after relaxation (sec. 9). */
 typedef struct {
     double s_XX, s_rx, s_eps, s_varpi, s_XXe;
     double Pr, E0, c1, k2, c_epsE, c_varpi_rho, c_varpi_E;
@@ -83,6 +84,7 @@ typedef struct {
     double g[2];
     double rho0;
     int collide;
+    double Q_E;
 } lbm13_params;
 
 /* Coefficients derived from lbm13_params by the constraints of eqs

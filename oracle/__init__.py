@@ -39,6 +39,7 @@ class Params(ctypes.Structure):
         ("F0x", ctypes.c_double), ("F0y", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("rho0", ctypes.c_double),
         ("collide", ctypes.c_int),
+        ("Q_E", ctypes.c_double),
     ]
 
 
@@ -105,7 +106,7 @@ def _p(a: np.ndarray):
 # A = 13 c1 + 95 + 2 E0 = 52, i.e. cs^2 = 1, and positive rest populations.
 DEFAULTS = dict(Pr=0.71, E0=-2.0, c1=-3.0, k2=-2.5, c_epsE=-2.5, c_varpi_rho=-6.0, c_varpi_E=-0.5,
                 s_XX=1.6, s_rx=1.05, s_eps=1.0, s_varpi=1.0, s_XXe=1.5,
-                F0x=0.0, F0y=0.0, gx=0.0, gy=0.0, rho0=1.0, collide=1)
+                F0x=0.0, F0y=0.0, gx=0.0, gy=0.0, rho0=1.0, collide=1, Q_E=0.0)
 
 
 def params(**kw) -> Params:

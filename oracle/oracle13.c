@@ -17,6 +17,8 @@
  *   - s_XY = s_XX, s_qy = s_qx, s_ry = s_rx (rates not listed for them), sec. 2.
  *   - body force added to j after relaxation, equilibria from pre-force j,
  *     no work term on E; u = (j + F/2)/rho on read-back, secs. 5 and 8.
+ *   - uniform energy source Q added to E after relaxation, equilibria from the
+ *     pre-source E, sec. 9.
  *   - walls are half a spacing outside the first/last node; links crossing a
  *     wall reverse their path (bounce-back of the whole velocity); links with a
  *     tangential component use bounce-back, links normal to a temperature wall
@@ -52,6 +54,7 @@ typedef struct {
     double F0x, F0y;                                       /* uniform body force, sec. 8 */
     double gx, gy, rho0;                                   /* buoyancy F = g (rho - rho0), sec. 5 */
     int collide;                                           /* 0: streaming and walls only */
+    double Q_E;                                            /* uniform volumic energy source, sec. 9 */
 } or13_params;
 
 typedef struct {
@@ -265,6 +268,7 @@ void or13_collide(int nx, int ny, const double *f, const or13_params *p, double 
         double Fy = p->F0y + p->gy * (m[M_RHO] - p->rho0);
         ms[M_JX] = m[M_JX] + Fx;
         ms[M_JY] = m[M_JY] + Fy;
+        ms[M_E] = m[M_E] + p->Q_E; /* energy source after relaxation (sec. 9) */
         moments_to_f(ms, fs);
         for (int i = 0; i < Q; ++i) fstar[i * n + c] = fs[i];
     }

@@ -368,6 +368,7 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
     D->F0y_d = F0y;
     D->gx_d = p->g[0];
     D->gy_d = p->g[1];
+    D->qE = R(p->Q_E / 4004.0);
     for (int w = 0; w < 4; ++w) {
         const double u = sides[w].u_tangential;
         D->wall_u[w] = R(u);

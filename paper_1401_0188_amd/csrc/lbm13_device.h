@@ -33,8 +33,9 @@ struct alignas(16) Dom {
     // q = j (a1 + h1 rho' + k1 E'), r = j (a2 + h2 rho' + k2 E'),  (rho', E' deviations)
     R c_er, c_eE, c_vr, c_vE;
     R a1, h1, k1, a2, h2, k2;
-    // body force F = F0 + g rho' (F0 already holds F0 + g (1 - rho0))
+    // body force F = F0 + g rho' (F0 already holds F0 + g (1 - rho0)); energy source
     R F0x, F0y, gx, gy;
+    R qE;  // Q_E / 4004: the energy source divided by the norm of the E moment
     // walls: tangential velocity, E_W - E0 for temperature walls
     R wall_u[4];
     R wall_dE[4];

@@ -49,7 +49,7 @@ __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >=
 // ---------------------------------------------------------------------------
 // Collision of one node, in place on the deviations g (sec. 2):
 //   m = M g; Delta_k = s_k (m_k - m_k^eq) on the nine non-conserved moments;
-//   j* = j + F; g* = g - M^T D^-1 Delta.
+//   j* = j + F (secs. 5, 8); E* = E + Q_E (sec. 9); g* = g - M^T D^-1 Delta.
 // Pairs (i, opposite of i) give sums s (even moments) and differences d (odd
 // moments); the inverse splits the same way.
 template <typename R>
@@ -91,14 +91,16 @@ __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
     const R bqx = D.s_q * (qx - jx * fq) * R(0.05), bqy = D.s_q * (qy - jy * fq) * R(0.05);
     const R brx = D.s_r * (rx - jx * fr) * R(1.0 / 70.0), bry = D.s_r * (ry - jy * fr) * R(1.0 / 70.0);
 
-    const R e0 = R(140) * aeps - R(12) * avp;
-    const R ec1 = R(-2) * aeps + R(8) * avp;
+    // the energy source enters as Delta_E = -Q_E (sec. 9)
+    const R aQ = D.qE;
+    const R e0 = R(140) * aeps - R(12) * avp + R(28) * aQ;
+    const R ec1 = R(-2) * aeps + R(8) * avp + R(15) * aQ;
     const R e1 = ec1 + aXX - R(4) * aXXe;
     const R e2 = ec1 - aXX + R(4) * aXXe;
-    const R ec5 = R(-67) * aeps - R(6) * avp;
+    const R ec5 = R(-67) * aeps - R(6) * avp + R(2) * aQ;
     const R e5 = ec5 + aXY;
     const R e6 = ec5 - aXY;
-    const R ec9 = R(34) * aeps + avp;
+    const R ec9 = R(34) * aeps + avp - R(24) * aQ;
     const R e9 = ec9 + R(4) * aXX + aXXe;
     const R e10 = ec9 - R(4) * aXX - aXXe;
     const R o1 = bjx - R(2) * bqx + R(4) * brx;

@@ -46,7 +46,7 @@ class Params(ctypes.Structure):
                 ("k2", ctypes.c_double), ("c_epsE", ctypes.c_double), ("c_varpi_rho", ctypes.c_double),
                 ("c_varpi_E", ctypes.c_double),
                 ("F0", ctypes.c_double * 2), ("g", ctypes.c_double * 2), ("rho0", ctypes.c_double),
-                ("collide", ctypes.c_int)]
+                ("collide", ctypes.c_int), ("Q_E", ctypes.c_double)]
 
 
 class Derived(ctypes.Structure):
@@ -59,7 +59,7 @@ class Derived(ctypes.Structure):
 # linear-stability scan of the dispersion relation, as the paper describes).
 DEFAULT_PARAMS = dict(s_XX=1.6, s_rx=1.05, s_eps=1.0, s_varpi=1.0, s_XXe=1.5, Pr=0.71, E0=-2.0, c1=-3.0,
                       k2=-2.5, c_epsE=-2.5, c_varpi_rho=-6.0, c_varpi_E=-0.5, F0=(0.0, 0.0), g=(0.0, 0.0),
-                      rho0=1.0, collide=1)
+                      rho0=1.0, collide=1, Q_E=0.0)
 
 _lib = None
 

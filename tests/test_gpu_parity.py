@@ -109,6 +109,7 @@ WALL_CASES = {
     "tiny_2x2": (2, 2, (2, 2, 1, 1), (0.01, 0, 0, 0), (-1.99, -2.01, 0, 0), dict(), 50),
     "y_walls_x_periodic": (37, 24, (0, 0, 2, 2), (0, 0, 0.02, 0), (0, 0, -1.99, -2.01), dict(g=(0.01, 0.0)), 200),
     "mixed_T_and_adiabatic": (70, 5, (2, 2, 1, 1), (0.01, 0.0, -0.01, 0.02), (-1.995, -2.0, 0, 0), dict(), 150),
+    "adiabatic_with_energy_source": (32, 6, (2, 1, 0, 0), (0.02, 0, 0, 0), (-2.0, 0, 0, 0), dict(Q_E=8e-6), 300),
 }
 
 

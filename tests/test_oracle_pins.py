@@ -496,3 +496,33 @@ def test_channel_startup_follows_series(kind, W, U, F):
         ref, scale = startup_poiseuille(xi, W, F, d["nu"], steps), F * W * W / (8 * d["nu"])
     assert np.abs(uy - ref).max() <= 5e-3 * scale
     assert np.abs(T - startup_conduction(xi, W, E0, dT, d["kappa"], steps)).max() <= 1e-2 * dT
+
+
+def test_energy_source_budget():
+    """Sec. 9 uniform volumic energy source: in a periodic box sum E grows by
+    exactly N Q per step while mass and momentum stay conserved."""
+    Q = 3e-6
+    p = oracle.params(Q_E=Q)
+    s = oracle.sides()
+    f0 = oracle.init(*workloads.periodic_wave(16), p)
+    t = 200
+    f1 = oracle.run(f0, p, s, t)
+    d0, d1 = oracle.diagnostics(f0, p, s), oracle.diagnostics(f1, p, s)
+    N = 16 * 16
+    assert abs(d1["sum_E"] - d0["sum_E"] - t * N * Q) < 1e-11 * N
+    assert abs(d1["sum_rho"] - d0["sum_rho"]) < 1e-12 * N
+
+
+def test_adiabatic_wall_with_energy_source_gives_semi_parabola():
+    """Sec. 9: temperature imposed on the West wall, adiabatic (bounce-back) East
+    wall, uniform source Q: T(xi) = T_W + (Q / kappa_E)(W xi - xi^2 / 2)."""
+    p = oracle.params()
+    st, d = oracle.derive(p)
+    W, Q = 16, 3.2e-5
+    s = oracle.sides((2, 1, 0, 0), (0, 0, 0, 0), (p.E0, 0, 0, 0))
+    pq = oracle.params(Q_E=Q)
+    f = oracle.run(oracle.init(*workloads.rest_fields(W, 2, p.E0), pq), pq, s, int(6 * W * W / d["kappa"]))
+    T = oracle.moments(f, pq)[3][0]
+    xi = np.arange(W) + 0.5
+    ref = p.E0 + Q / d["kappa_E"] * (W * xi - xi ** 2 / 2)
+    assert np.abs(T - ref).max() <= 0.01 * (ref - p.E0).max()
