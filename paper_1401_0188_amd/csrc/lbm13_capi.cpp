@@ -369,6 +369,8 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
     D->gx_d = p->g[0];
     D->gy_d = p->g[1];
     D->qE = R(p->Q_E / 4004.0);
+    D->QE = R(p->Q_E);
+    D->QE_d = p->Q_E;
     for (int w = 0; w < 4; ++w) {
         const double u = sides[w].u_tangential;
         D->wall_u[w] = R(u);

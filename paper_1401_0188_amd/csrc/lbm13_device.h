@@ -36,6 +36,7 @@ struct alignas(16) Dom {
     // body force F = F0 + g rho' (F0 already holds F0 + g (1 - rho0)); energy source
     R F0x, F0y, gx, gy;
     R qE;  // Q_E / 4004: the energy source divided by the norm of the E moment
+    R QE;  // Q_E: the kept post-collision state carries E(t) + Q_E
     // walls: tangential velocity, E_W - E0 for temperature walls
     R wall_u[4];
     R wall_dE[4];
@@ -44,6 +45,7 @@ struct alignas(16) Dom {
     double frest[4];  // rest populations of the |v|^2 = 0, 1, 2, 4 classes
     double F0x_d, F0y_d, gx_d, gy_d;
     double B;         // equilibrium E flux per unit momentum
+    double QE_d;      // Q_E in FP64
     double nu_scale;  // nx / (kappa_E (T_W - T_E)), 0 when T_W == T_E
 };
 

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void side_fill_kernel(const R* __restrict__ sr
     node_rho_E(b, D, c1, r1, e1);
     R* o = side_line(side, D, buf, wl.line);
     o[0] = r0;
-    o[1] = e0;
+    o[1] = e0 - D.QE;  // E(t): the kept post-collision state carries E(t) + Q_E
     o[2] = r1;
     o[3] = R(0);
 }
@@ -403,14 +403,15 @@ __device__ __forceinline__ void gather_wall(const Src& A, const Side& SD, const 
 }
 
 // After collision, a node in the first or second layer of a wall records its
-// rho' (and E' for the first layer) for the next step's wall states.
+// rho' (and E' for the first layer, without this step's energy source) for the
+// next step's wall states.
 template <typename R>
 __device__ __forceinline__ void record_wall_layers(R* __restrict__ side, const Dom<R>& D, int buf, int x, int y,
                                                    const R g[13]) {
     const bool xw = !D.xper && (x < 2 || x >= D.nx - 2);
     const bool yw = !D.yper && (y < 2 || y >= D.ny - 2);
     if (!xw && !yw) return;
-    R rho = R(0), E = R(0);
+    R rho = R(0), E = -D.QE;
 #pragma unroll
     for (int i = 0; i < 13; ++i) {
         rho += g[i];
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(256) void step2_kernel(const R* __restrict__ src, R
 #pragma unroll
         for (int i = 0; i < 13; ++i) lds[(i * RH + ly) * RW + lx] = g[i];
         if (xw || yw) {
-            R rho = R(0), E = R(0);
+            R rho = R(0), E = -D.QE;
 #pragma unroll
             for (int i = 0; i < 13; ++i) {
                 rho += g[i];
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(256) void init_kernel(R* __restrict__ dst, const Do
 }
 
 // ---------------------------------------------------------------------------
-// Read-back at time t from the kept f*(t): rho = 1 + sum g, E = E0 + sum M_E g,
+// Read-back at time t from the kept f*(t): rho = 1 + sum g, E = E0 + sum M_E g - Q_E,
 // j = j* - F, u = (j + F/2)/rho = (j* - F/2)/rho, T = E - 13/2 |u|^2 (sec. 7).
 template <typename R>
 __device__ __forceinline__ void node_macro(const R* __restrict__ a, const Dom<R>& D, int c, double& rho, double& ux,
@@ -641,7 +642,7 @@ __device__ __forceinline__ void node_macro(const R* __restrict__ a, const Dom<R>
     rho = 1.0 + r;
     ux = (jx - 0.5 * Fx) / rho;
     uy = (jy - 0.5 * Fy) / rho;
-    T = D.E0 + e - 6.5 * (ux * ux + uy * uy);
+    T = D.E0 + (e - D.QE_d) - 6.5 * (ux * ux + uy * uy);
 }
 
 template <typename R>
@@ -754,7 +755,7 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(const R* __restrict__
         acc[0] += rp;
         acc[1] += jx - Fx;
         acc[2] += jy - Fy;
-        acc[3] += e;
+        acc[3] += e - D.QE_d;
         acc[4] += heat;
         const double rho = 1.0 + rp;
         const double ux = (jx - 0.5 * Fx) / rho, uy = (jy - 0.5 * Fy) / rho;
