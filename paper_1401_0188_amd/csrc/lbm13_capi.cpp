@@ -469,6 +469,8 @@ int step_impl(lbm13_batch* b, long long n) {
         }
         hipError_t e = hipGraphLaunch(b->gexec[b->cur], b->stream);
         if (e != hipSuccess) return hip_fail(b, e, "graph launch");
+        // each launch in the graph swaps the buffers once
+        if ((b->graph_k / b->spl) % 2 == 1) b->cur = 1 - b->cur;
         n -= b->graph_k;
         b->steps += b->graph_k;
     }
