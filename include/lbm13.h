@@ -191,6 +191,12 @@ int lbm13_use_graph(lbm13_ctx *ctx, int k);
  * done by a single-step launch.  EINVAL for other values. */
 int lbm13_set_steps_per_launch(lbm13_ctx *ctx, int k);
 
+/* Tile of the two-steps-per-launch kernel: (64, 12), (64, 8), (64, 4),
+ * (32, 16), (32, 8) or (32, 4) nodes, of which FP64 accepts the shapes whose
+ * region (tile + 2-node halo) x 13 populations fits 64 KB of LDS: (64, 4),
+ * (32, 8), (32, 4).  Defaults: (64, 12) FP32, (32, 8) FP64.  EINVAL otherwise. */
+int lbm13_set_fused_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
+
 /* Destroy the context (frees host objects and graphs; never the workspace). */
 int lbm13_destroy(lbm13_ctx *ctx);
 
@@ -225,6 +231,7 @@ int lbm13_batch_set_tile(lbm13_batch *b, int tile_x, int tile_y);
 int lbm13_batch_autotune(lbm13_batch *b, int steps, int *tile_x, int *tile_y);
 int lbm13_batch_use_graph(lbm13_batch *b, int k);
 int lbm13_batch_set_steps_per_launch(lbm13_batch *b, int k);
+int lbm13_batch_set_fused_tile(lbm13_batch *b, int tile_x, int tile_y);
 long long lbm13_batch_nodes(const lbm13_batch *b);
 int lbm13_batch_destroy(lbm13_batch *b);
 const char *lbm13_batch_last_error(const lbm13_batch *b);

@@ -29,7 +29,7 @@ hipError_t launch_step(int, int, const R*, R*, const Dom<R>*, const Tile*, int, 
 template <typename R>
 hipError_t launch_side_fill(const R*, const Dom<R>*, const WallLine*, int, R*, int, int, hipStream_t);
 template <typename R>
-hipError_t launch_step2(const R*, R*, const Dom<R>*, const Tile*, int, R*, int, hipStream_t);
+hipError_t launch_step2(int, int, const R*, R*, const Dom<R>*, const Tile*, int, R*, int, hipStream_t);
 template <typename R>
 hipError_t launch_diag(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, double*, hipStream_t);
 template <typename R>
@@ -52,6 +52,13 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kCoef = 16;  // doubles of init coefficients per domain
 const int kShapes[][2] = {{64, 4}, {64, 8}, {64, 16}, {32, 8}, {32, 16}};
+// fused (two steps per launch) tile shapes; FP64 only those whose region fits LDS
+const int kFusedShapes[][2] = {{64, 12}, {64, 8}, {64, 4}, {32, 16}, {32, 8}, {32, 4}};
+
+bool fused_fits(int precision, int tw, int th) {
+    const int es = precision == LBM13_FP64 ? 8 : 4;
+    return 13 * (tw + 4) * (th + 4) * es + 6 * (tw + th + 8) * es <= 65536;
+}
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -81,8 +88,6 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
     L.pitch.resize(count);
     L.plane.resize(count);
     long long tmax = 0, tfmax = 0, lines = 0;
-    const int ftw = precision == LBM13_FP64 ? lbm13::Fused<double>::TW : lbm13::Fused<float>::TW;
-    const int fth = precision == LBM13_FP64 ? lbm13::Fused<double>::TH : lbm13::Fused<float>::TH;
     size_t elems = 0;
     for (int d = 0; d < count; ++d) {
         if (nx[d] < 2 || ny[d] < 2 || nx[d] > (1 << 16) || ny[d] > (1 << 16)) return false;
@@ -99,7 +104,10 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
         for (auto& s : kShapes)
             t = std::max(t, (long long)((nx[d] + s[0] - 1) / s[0]) * ((ny[d] + s[1] - 1) / s[1]));
         tmax += t;
-        tfmax += (long long)((nx[d] + ftw - 1) / ftw) * ((ny[d] + fth - 1) / fth);
+        long long tf = 0;
+        for (auto& f : kFusedShapes)
+            tf = std::max(tf, (long long)((nx[d] + f[0] - 1) / f[0]) * ((ny[d] + f[1] - 1) / f[1]));
+        tfmax += tf;
     }
     if (tmax >= INT32_MAX / 2 || tfmax >= INT32_MAX / 2) return false;
     L.tmax = (int)tmax;
@@ -180,6 +188,7 @@ struct lbm13_batch {
     std::vector<Tile> all, run, fused;
     std::vector<WallLine> lines;
     int spl = 1;                          // time steps per launch (1 or 2)
+    int ftw = 64, fth = 12;               // fused tile shape
     int nbulk = 0, nedge = 0;
     int tile_x = 64, tile_y = 8;
     int cur = 0;                          // buffer holding the current state
@@ -273,14 +282,10 @@ int rebuild(lbm13_batch* b) {
     b->run = bulk;
     b->run.insert(b->run.end(), edge.begin(), edge.end());
     b->fused.clear();
-    {
-        const int ftw = b->precision == LBM13_FP64 ? lbm13::Fused<double>::TW : lbm13::Fused<float>::TW;
-        const int fth = b->precision == LBM13_FP64 ? lbm13::Fused<double>::TH : lbm13::Fused<float>::TH;
-        for (int d = 0; d < b->count; ++d)
-            for (int y0 = 0; y0 < b->ny[d]; y0 += fth)
-                for (int x0 = 0; x0 < b->nx[d]; x0 += ftw) b->fused.push_back(Tile{d, x0, y0, 0});
-        if ((int)b->fused.size() > b->L.tfmax) return fail(b, LBM13_EINVAL, "fused tile table overflow");
-    }
+    for (int d = 0; d < b->count; ++d)
+        for (int y0 = 0; y0 < b->ny[d]; y0 += b->fth)
+            for (int x0 = 0; x0 < b->nx[d]; x0 += b->ftw) b->fused.push_back(Tile{d, x0, y0, 0});
+    if ((int)b->fused.size() > b->L.tfmax) return fail(b, LBM13_EINVAL, "fused tile table overflow");
     b->lines.clear();
     for (int d = 0; d < b->count; ++d) {
         const int* k = &b->sides_kind[4 * d];
@@ -401,8 +406,8 @@ template <typename R>
 hipError_t launch_two_steps(lbm13_batch* b, int from, hipStream_t s) {
     const Tile* tiles = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_fused);
     R* side = reinterpret_cast<R*>(b->ws + b->L.wall);
-    return lbm13::launch_step2<R>(buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), tiles, (int)b->fused.size(),
-                                  side, from, s);
+    return lbm13::launch_step2<R>(b->ftw, b->fth, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), tiles,
+                                  (int)b->fused.size(), side, from, s);
 }
 
 // Wall-layer side values of the kept state (after init, set_state, load).
@@ -581,6 +586,8 @@ int lbm13_batch_create(int count, const int* nx, const int* ny, int precision, v
     b->sides_kind.assign(4 * count, LBM13_PERIODIC);
     b->has_params.assign(count, 0);
     b->has_state.assign(count, 0);
+    b->ftw = precision == LBM13_FP64 ? lbm13::Fused<double>::TW : lbm13::Fused<float>::TW;
+    b->fth = precision == LBM13_FP64 ? lbm13::Fused<double>::TH : lbm13::Fused<float>::TH;
     int st = rebuild(b);
     if (st) {
         delete b;
@@ -782,6 +789,17 @@ int lbm13_batch_use_graph(lbm13_batch* b, int k) {
     return LBM13_OK;
 }
 
+int lbm13_batch_set_fused_tile(lbm13_batch* b, int tile_x, int tile_y) {
+    if (!b) return LBM13_EINVAL;
+    bool ok = false;
+    for (auto& f : kFusedShapes) ok = ok || (f[0] == tile_x && f[1] == tile_y);
+    if (!ok || !fused_fits(b->precision, tile_x, tile_y))
+        return fail(b, LBM13_EINVAL, "unsupported two-step tile shape for this precision");
+    b->ftw = tile_x;
+    b->fth = tile_y;
+    return rebuild(b);
+}
+
 int lbm13_batch_set_steps_per_launch(lbm13_batch* b, int k) {
     if (!b) return LBM13_EINVAL;
     if (k != 1 && k != 2) return fail(b, LBM13_EINVAL, "steps per launch must be 1 or 2");
@@ -867,6 +885,10 @@ int lbm13_autotune(lbm13_ctx* c, int steps, int* tile_x, int* tile_y) {
 }
 
 int lbm13_use_graph(lbm13_ctx* c, int k) { return c ? lbm13_batch_use_graph(c->b, k) : LBM13_EINVAL; }
+
+int lbm13_set_fused_tile(lbm13_ctx* c, int tile_x, int tile_y) {
+    return c ? lbm13_batch_set_fused_tile(c->b, tile_x, tile_y) : LBM13_EINVAL;
+}
 
 int lbm13_set_steps_per_launch(lbm13_ctx* c, int k) {
     return c ? lbm13_batch_set_steps_per_launch(c->b, k) : LBM13_EINVAL;

@@ -63,8 +63,9 @@ struct alignas(16) WallLine {
     int dom, w, pos, line;
 };
 
-// Tile of the two-steps-per-launch kernel: the region (TW + 4) x (TH + 4) x 13
-// populations must fit the 64 KB of LDS a workgroup can address.
+// Tiles of the two-steps-per-launch kernel.  The region (TW + 4) x (TH + 4) x
+// 13 populations must fit the 64 KB of LDS a workgroup can address; Fused<R>
+// is the default shape, FusedFits tells which compiled shapes fit.
 template <typename R>
 struct Fused;
 template <>
@@ -74,6 +75,10 @@ struct Fused<float> {
 template <>
 struct Fused<double> {
     static constexpr int TW = 32, TH = 8;
+};
+template <typename R, int TW, int TH>
+struct FusedFits {
+    static constexpr bool value = 13 * (TW + 4) * (TH + 4) * sizeof(R) + 6 * (TW + TH + 8) * sizeof(R) <= 65536;
 };
 
 constexpr int kDiagPartials = 10;  // per-tile partial reductions

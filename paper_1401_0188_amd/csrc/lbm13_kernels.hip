@@ -518,9 +518,10 @@ __global__ __launch_bounds__(256) void step2_kernel(const R* __restrict__ src, R
     for (int r = tid; r < RW * RH; r += NT) {
         const int lx = r % RW, ly = r / RW;
         int X = ox + lx, Y = oy + ly;
-        if (D.xper) X = pmod(X, D.nx);
+        // a region wraps at most once around an axis at least as long as itself
+        if (D.xper) X = D.nx >= RW ? wrap(X, D.nx) : pmod(X, D.nx);
         else if (X < 0 || X >= D.nx) continue;
-        if (D.yper) Y = pmod(Y, D.ny);
+        if (D.yper) Y = D.ny >= RH ? wrap(Y, D.ny) : pmod(Y, D.ny);
         else if (Y < 0 || Y >= D.ny) continue;
         R g[13];
         const bool xw = !D.xper && (X < 2 || X >= D.nx - 2);
@@ -888,12 +889,24 @@ hipError_t launch_diag(int tile_x, int tile_y, const R* src, const Dom<R>* doms,
 }
 
 template <typename R>
-hipError_t launch_step2(const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int ntiles, R* side, int from,
-                        hipStream_t s) {
+hipError_t launch_step2(int tw, int th, const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int ntiles,
+                        R* side, int from, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    constexpr int TW = Fused<R>::TW, TH = Fused<R>::TH;
-    step2_kernel<R, TW, TH><<<ntiles, dim3(64, 4), 0, s>>>(src, dst, doms, tiles, ntiles, side, from);
-    return hipGetLastError();
+    const dim3 blk(64, 4);
+#define LBM13_FUSED(TW, TH)                                                                        \
+    if (tw == TW && th == TH && FusedFits<R, TW, TH>::value) {                                     \
+        step2_kernel<R, TW, (FusedFits<R, TW, TH>::value ? TH : 1)><<<ntiles, blk, 0, s>>>(       \
+            src, dst, doms, tiles, ntiles, side, from);                                            \
+        return hipGetLastError();                                                                  \
+    }
+    LBM13_FUSED(64, 12)
+    LBM13_FUSED(64, 8)
+    LBM13_FUSED(64, 4)
+    LBM13_FUSED(32, 16)
+    LBM13_FUSED(32, 8)
+    LBM13_FUSED(32, 4)
+#undef LBM13_FUSED
+    return hipErrorInvalidValue;
 }
 
 template <typename R>
@@ -937,7 +950,8 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
 #define LBM13_INSTANTIATE(R)                                                                                      \
     template hipError_t launch_step<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, \
                                        R*, int, hipStream_t);                                                     \
-    template hipError_t launch_step2<R>(const R*, R*, const Dom<R>*, const Tile*, int, R*, int, hipStream_t);       \
+    template hipError_t launch_step2<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, R*, int,          \
+                                        hipStream_t);                                                             \
     template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, int,          \
                                             hipStream_t);                                                         \
     template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*,         \

@@ -27,6 +27,8 @@ WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 DIAG_NAMES = ("sum_rho", "sum_jx", "sum_jy", "sum_E", "heat_flux", "Nu_mean", "u_max", "asym_abs",
               "asym_rel", "nonfinite", "rho_min")
 TILE_SHAPES = ((64, 4), (64, 8), (64, 16), (32, 8), (32, 16))
+FUSED_TILE_SHAPES = {FP32_DEV: ((64, 12), (64, 8), (64, 4), (32, 16), (32, 8), (32, 4)),
+                     FP64: ((64, 4), (32, 8), (32, 4))}
 
 
 class LBM13Error(RuntimeError):
@@ -94,6 +96,7 @@ def lib():
         "lbm13_autotune": (i32, [vp, i32, ip, ip]),
         "lbm13_use_graph": (i32, [vp, i32]),
         "lbm13_set_steps_per_launch": (i32, [vp, i32]),
+        "lbm13_set_fused_tile": (i32, [vp, i32, i32]),
         "lbm13_destroy": (i32, [vp]),
         "lbm13_last_error": (ctypes.c_char_p, [vp]),
         "lbm13_batch_workspace_bytes": (sz, [i32, ip, ip, i32]),
@@ -112,6 +115,7 @@ def lib():
         "lbm13_batch_autotune": (i32, [vp, i32, ip, ip]),
         "lbm13_batch_use_graph": (i32, [vp, i32]),
         "lbm13_batch_set_steps_per_launch": (i32, [vp, i32]),
+        "lbm13_batch_set_fused_tile": (i32, [vp, i32, i32]),
         "lbm13_batch_nodes": (i64, [vp]),
         "lbm13_batch_destroy": (i32, [vp]),
         "lbm13_batch_last_error": (ctypes.c_char_p, [vp]),
@@ -275,6 +279,9 @@ class Lattice(_Base):
     def set_steps_per_launch(self, k: int):
         self._check(lib().lbm13_set_steps_per_launch(self._h, int(k)))
 
+    def set_fused_tile(self, tile_x: int, tile_y: int):
+        self._check(lib().lbm13_set_fused_tile(self._h, int(tile_x), int(tile_y)))
+
     def destroy(self):
         if getattr(self, "_h", None):
             lib().lbm13_destroy(self._h)
@@ -383,6 +390,9 @@ class Batch(_Base):
 
     def set_steps_per_launch(self, k: int):
         self._check(lib().lbm13_batch_set_steps_per_launch(self._h, int(k)))
+
+    def set_fused_tile(self, tile_x: int, tile_y: int):
+        self._check(lib().lbm13_batch_set_fused_tile(self._h, int(tile_x), int(tile_y)))
 
     def nodes(self) -> int:
         return int(lib().lbm13_batch_nodes(self._h))
