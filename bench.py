@@ -23,7 +23,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-BENCH_TILE = (64, 8)          # tile shape of the step kernel timed here
+# Launch configuration timed here: two time steps per launch (tile + halo in
+# LDS), with the two-step tile of each precision; the single-step tile is used
+# for the plain single-step FP64 comparison.
+BENCH_CONFIG = {1: dict(spl=2, fused_tile=(32, 16), tile=(64, 8)),
+                0: dict(spl=2, fused_tile=(32, 8), tile=(64, 8))}
+BENCH_TILE = BENCH_CONFIG[1]["tile"]
 GRAPH_K = 100                 # steps per captured HIP graph
 BYTES_PER_LU = {0: 208, 1: 104}  # 13 loads + 13 stores of populations, FP64 / FP32
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E
@@ -41,27 +46,29 @@ def kernel_sha():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(precision):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+def measured_traffic(key):
+    """HBM bytes per launch of the timed kernel from the committed rocprofv3
+    counter runs, if they were taken on the current kernel source; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    rec = t.get("fp32" if precision == 1 else "fp64")
+    rec = t.get(key)
     if not rec or t.get("kernel_source_sha") != kernel_sha():
         return None
     return rec.get("bytes_per_launch")
 
 
-def run_form(precision, n, steps, warmup, diag_every, tile, graph_k):
+def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k):
     import torch
 
     from paper_1401_0188_amd import lbm13, workloads
     stream = torch.cuda.current_stream()
     lat = lbm13.Lattice(n, n, precision, stream=stream)
-    lat.set_tile(*tile)
+    lat.set_tile(*cfg["tile"])
+    lat.set_fused_tile(*cfg["fused_tile"])
+    lat.set_steps_per_launch(cfg["spl"])
     lat.set_params()
     lat.init_moments(*workloads.shear_acoustic(n))
     if graph_k:
@@ -93,9 +100,10 @@ def run_form(precision, n, steps, warmup, diag_every, tile, graph_k):
     lat.destroy()
     del lat
     torch.cuda.empty_cache()
-    return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=kern_ms / steps,
+    spl = cfg["spl"]
+    return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=kern_ms / steps * spl,
                 mlups=nodes * steps / wall / 1e6, kernel_mlups=nodes / (kern_ms / steps * 1e-3) / 1e6,
-                mass_drift=drift, nodes=nodes)
+                mass_drift=drift, nodes=nodes, spl=spl)
 
 
 def cavity_specs(count=64, seed=4):
@@ -159,11 +167,15 @@ def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=Tru
     import torch
     b = build_batch(specs, precision)
     tile = None
+    cfg = None
     if autotune:
-        tile = b.autotune(10)
+        b.autotune(10)
+        cfg = b.launch_config()
         b.destroy()
         b = build_batch(specs, precision)  # fresh state after tuning
-        b.set_tile(*tile)
+        b.set_tile(*cfg["tile"])
+        b.set_fused_tile(*cfg["fused_tile"])
+        b.set_steps_per_launch(cfg["steps_per_launch"])
     if graph_k:
         b.use_graph(graph_k)
     b.step(warmup)
@@ -191,8 +203,9 @@ def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=Tru
     nodes = b.nodes()
     b.destroy()
     torch.cuda.empty_cache()
-    return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=kern_ms / steps,
-                mlups=nodes * steps / wall / 1e6, nodes=nodes, tile=tile, diag=diag)
+    spl = cfg["steps_per_launch"] if cfg else 1
+    return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=kern_ms / steps * spl,
+                mlups=nodes * steps / wall / 1e6, nodes=nodes, cfg=cfg, spl=spl, diag=diag)
 
 
 def run_sequential_fp64(specs, steps):
@@ -263,10 +276,15 @@ def cpu_baseline(n, budget_s):
                 sample="%d steps of the %dx%d periodic shear + acoustic wave, FP64 oracle, %.1f s" % (steps, n, n, el))
 
 
-def roofline(nodes, kernel_ms, precision, traffic=None):
-    achieved = BYTES_PER_LU[precision] * nodes / (kernel_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic}
+def roofline(nodes, kernel_ms, precision, traffic=None, spl=1):
+    """Algorithmic bytes per launch (26 population moves per lattice update,
+    spl updates per node per launch) over the launch's duration."""
+    achieved = BYTES_PER_LU[precision] * nodes * spl / (kernel_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic}
+    if traffic:
+        out["traffic_GBps"] = round(traffic / (kernel_ms * 1e-3) / 1e9, 1)
+    return out
 
 
 def cpu_baseline_spec(spec, budget_s):
@@ -299,7 +317,8 @@ def main_batched(args, copy_gbps):
     graph_k = 0 if args.no_graph else GRAPH_K
     log("%s: %d domains, batched fp32-deviation, %d steps" % (args.workload, len(specs), args.steps))
     r32 = run_batch(specs, lbm13.FP32_DEV, args.steps, args.warmup, args.diag_every, graph_k)
-    log("batched fp32: %.1f MLUPS, kernel %.4f ms, tile %s" % (r32["mlups"], r32["kernel_ms_per_launch"], r32["tile"]))
+    log("batched fp32: %.1f MLUPS, kernel %.4f ms per launch, config %s" % (r32["mlups"], r32["kernel_ms_per_launch"],
+                                                                          r32["cfg"]))
     fp64_steps = args.fp64_steps if args.fp64_steps >= 0 else max(1, args.steps // 4)
     log("sequential plain fp64: %d steps" % fp64_steps)
     r64 = run_sequential_fp64(specs, fp64_steps)
@@ -315,9 +334,9 @@ def main_batched(args, copy_gbps):
         "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "%s: %d domains, %d nodes" % (args.workload, len(specs), r32["nodes"]),
-                   "form": "fp32-deviation batched, one launch per step", "tile": r32["tile"],
+                   "form": "fp32-deviation batched, one launch covers every domain", "launch": r32["cfg"],
                    "graph_steps": graph_k, "diag_every": args.diag_every, "clamped_domains": clamped},
-        "roofline": roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1),
+        "roofline": roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, spl=r32["spl"]),
         "cpu_baseline": cpu,
         "fp64_sequential": {"value": round(r64["mlups"], 1), "unit": "MLUPS",
                             "ms_per_step": round(r64["ms_per_step"], 5), "steps": fp64_steps,
@@ -364,20 +383,24 @@ def main():
     n = args.size
     graph_k = 0 if args.no_graph else GRAPH_K
     log("fp32-deviation %dx%d: %d warmup + %d steps" % (n, n, args.warmup, args.steps))
-    r32 = run_form(lbm13.FP32_DEV, n, args.steps, args.warmup, args.diag_every, BENCH_TILE, graph_k)
-    log("fp32: %.1f MLUPS, kernel %.4f ms" % (r32["mlups"], r32["kernel_ms_per_launch"]))
-    fp64_steps = args.fp64_steps if args.fp64_steps >= 0 else max(1, args.steps // 2)
+    r32 = run_form(lbm13.FP32_DEV, n, args.steps, args.warmup, args.diag_every, BENCH_CONFIG[1], graph_k)
+    log("fp32: %.1f MLUPS, kernel %.4f ms per launch" % (r32["mlups"], r32["kernel_ms_per_launch"]))
+    fp64_steps = args.fp64_steps if args.fp64_steps >= 0 else max(2, args.steps // 2)
     log("fp64 %dx%d: %d steps" % (n, n, fp64_steps))
-    r64 = run_form(lbm13.FP64, n, fp64_steps, max(1, args.warmup // 2), args.diag_every, BENCH_TILE, graph_k)
-    log("fp64: %.1f MLUPS, kernel %.4f ms" % (r64["mlups"], r64["kernel_ms_per_launch"]))
+    r64 = run_form(lbm13.FP64, n, fp64_steps, max(2, args.warmup // 2), args.diag_every, BENCH_CONFIG[0], graph_k)
+    log("fp64: %.1f MLUPS, kernel %.4f ms per launch" % (r64["mlups"], r64["kernel_ms_per_launch"]))
+    plain_cfg = dict(BENCH_CONFIG[0], spl=1)
+    r64p = run_form(lbm13.FP64, n, fp64_steps, max(2, args.warmup // 2), args.diag_every, plain_cfg, graph_k)
+    log("fp64 one step per launch: %.1f MLUPS, kernel %.4f ms" % (r64p["mlups"], r64p["kernel_ms_per_launch"]))
 
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) for about %.0f s" % args.cpu_seconds)
         cpu = cpu_baseline(n, args.cpu_seconds)
 
-    roof32 = roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, measured_traffic(1))
-    roof64 = roofline(r64["nodes"], r64["kernel_ms_per_launch"], 0, measured_traffic(0))
+    roof32 = roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, measured_traffic("fp32_two_step"), spl=2)
+    roof64 = roofline(r64["nodes"], r64["kernel_ms_per_launch"], 0, measured_traffic("fp64_two_step"), spl=2)
+    roof64p = roofline(r64p["nodes"], r64p["kernel_ms_per_launch"], 0, measured_traffic("fp64"), spl=1)
     out = {
         "metric": METRIC,
         "value": round(r32["mlups"], 1),
@@ -392,18 +415,24 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "periodic %dx%d transverse shear + acoustic wave" % (n, n), "nx": n, "ny": n,
-                   "form": "fp32-deviation", "tile": list(BENCH_TILE), "graph_steps": graph_k,
+                   "form": "fp32-deviation, two steps per launch",
+                   "fused_tile": list(BENCH_CONFIG[1]["fused_tile"]), "graph_steps": graph_k,
                    "diag_every": args.diag_every},
         "roofline": roof32,
         "cpu_baseline": cpu,
         "fp64": {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
-                 "roofline": roof64, "steps": fp64_steps},
+                 "roofline": roof64, "steps": fp64_steps, "form": "fp64, two steps per launch"},
+        "fp64_plain": {"value": round(r64p["mlups"], 1), "unit": "MLUPS",
+                       "ms_per_step": round(r64p["ms_per_step"], 5), "roofline": roof64p,
+                       "form": "fp64, one step per launch"},
         "speedup_vs_fp64": round(r32["mlups"] / r64["mlups"], 3),
+        "speedup_vs_fp64_plain": round(r32["mlups"] / r64p["mlups"], 3),
         "kernel_ms_per_launch": {"fp32": round(r32["kernel_ms_per_launch"], 5),
-                                 "fp64": round(r64["kernel_ms_per_launch"], 5)},
+                                 "fp64": round(r64["kernel_ms_per_launch"], 5),
+                                 "fp64_plain": round(r64p["kernel_ms_per_launch"], 5)},
         "copy_GBps": round(copy_gbps, 1),
         "frac_of_copy": round(roof32["achieved"] / copy_gbps, 4),
-        "mass_drift": {"fp32": r32["mass_drift"], "fp64": r64["mass_drift"]},
+        "mass_drift": {"fp32": r32["mass_drift"], "fp64": r64["mass_drift"], "fp64_plain": r64p["mass_drift"]},
         "kernel_source_sha": kernel_sha(),
     }
     print(json.dumps(out), flush=True)

@@ -175,10 +175,16 @@ long long lbm13_steps_done(const lbm13_ctx *ctx);
  * for unsupported shapes. */
 int lbm13_set_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
 
-/* Time every supported tile shape for `steps` steps on the current state
- * (state is advanced, so save it first if needed) and keep the fastest.
- * Writes the chosen shape to tile_x/tile_y when not NULL.  Synchronises. */
+/* Time every supported launch configuration (single-step tile shapes and
+ * two-steps-per-launch tile shapes) for `steps` steps on the current state
+ * (the state is advanced, so save it first if needed) and keep the fastest.
+ * Writes the chosen kernel's tile shape to tile_x/tile_y when not NULL (see
+ * lbm13_launch_config for the whole choice).  Synchronises. */
 int lbm13_autotune(lbm13_ctx *ctx, int steps, int *tile_x, int *tile_y);
+
+/* Current launch configuration: cfg = {steps per launch, single-step tile_x,
+ * tile_y, two-step tile_x, tile_y}.  Host-only. */
+int lbm13_launch_config(const lbm13_ctx *ctx, int cfg[5]);
 
 /* Capture k steps (k even, 2..4096) into a HIP graph that lbm13_step() then
  * replays for every full block of k steps; k = 0 switches graphs off. */
@@ -194,7 +200,7 @@ int lbm13_set_steps_per_launch(lbm13_ctx *ctx, int k);
 /* Tile of the two-steps-per-launch kernel: (64, 12), (64, 8), (64, 4),
  * (32, 16), (32, 8) or (32, 4) nodes, of which FP64 accepts the shapes whose
  * region (tile + 2-node halo) x 13 populations fits 64 KB of LDS: (64, 4),
- * (32, 8), (32, 4).  Defaults: (64, 12) FP32, (32, 8) FP64.  EINVAL otherwise. */
+ * (32, 8), (32, 4).  Defaults: (32, 16) FP32, (32, 8) FP64.  EINVAL otherwise. */
 int lbm13_set_fused_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
 
 /* Destroy the context (frees host objects and graphs; never the workspace). */
@@ -232,6 +238,7 @@ int lbm13_batch_autotune(lbm13_batch *b, int steps, int *tile_x, int *tile_y);
 int lbm13_batch_use_graph(lbm13_batch *b, int k);
 int lbm13_batch_set_steps_per_launch(lbm13_batch *b, int k);
 int lbm13_batch_set_fused_tile(lbm13_batch *b, int tile_x, int tile_y);
+int lbm13_batch_launch_config(const lbm13_batch *b, int cfg[5]);
 long long lbm13_batch_nodes(const lbm13_batch *b);
 int lbm13_batch_destroy(lbm13_batch *b);
 const char *lbm13_batch_last_error(const lbm13_batch *b);

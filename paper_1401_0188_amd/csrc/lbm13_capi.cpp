@@ -511,12 +511,26 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
         return fail(b, LBM13_EDEVICE, "event create");
     const int keep_k = b->graph_k;
     b->graph_k = 0;
+    steps += steps & 1;  // an even count keeps two-step launches whole
+    struct Cand {
+        int spl, w, h;
+    };
+    std::vector<Cand> cands;
+    for (auto& s : kShapes) cands.push_back(Cand{1, s[0], s[1]});
+    for (auto& f : kFusedShapes)
+        if (fused_fits(b->precision, f[0], f[1])) cands.push_back(Cand{2, f[0], f[1]});
     float best = 1e30f;
-    int bx = b->tile_x, by = b->tile_y;
+    Cand pick{b->spl, b->spl == 2 ? b->ftw : b->tile_x, b->spl == 2 ? b->fth : b->tile_y};
     int st = LBM13_OK;
-    for (auto& s : kShapes) {
-        b->tile_x = s[0];
-        b->tile_y = s[1];
+    for (const Cand& c : cands) {
+        b->spl = c.spl;
+        if (c.spl == 1) {
+            b->tile_x = c.w;
+            b->tile_y = c.h;
+        } else {
+            b->ftw = c.w;
+            b->fth = c.h;
+        }
         if ((st = rebuild(b))) break;
         if ((st = step_impl<R>(b, 2))) break;
         (void)hipEventRecord(e0, b->stream);
@@ -530,20 +544,25 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best) {
             best = ms;
-            bx = s[0];
-            by = s[1];
+            pick = c;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    b->tile_x = bx;
-    b->tile_y = by;
+    b->spl = pick.spl;
+    if (pick.spl == 1) {
+        b->tile_x = pick.w;
+        b->tile_y = pick.h;
+    } else {
+        b->ftw = pick.w;
+        b->fth = pick.h;
+    }
     int st2 = rebuild(b);
     b->graph_k = keep_k;
     if (st) return st;
     if (st2) return st2;
-    if (tx) *tx = bx;
-    if (ty) *ty = by;
+    if (tx) *tx = pick.w;
+    if (ty) *ty = pick.h;
     return LBM13_OK;
 }
 
@@ -808,6 +827,16 @@ int lbm13_batch_set_steps_per_launch(lbm13_batch* b, int k) {
     return LBM13_OK;
 }
 
+int lbm13_batch_launch_config(const lbm13_batch* b, int cfg[5]) {
+    if (!b || !cfg) return LBM13_EINVAL;
+    cfg[0] = b->spl;
+    cfg[1] = b->tile_x;
+    cfg[2] = b->tile_y;
+    cfg[3] = b->ftw;
+    cfg[4] = b->fth;
+    return LBM13_OK;
+}
+
 long long lbm13_batch_nodes(const lbm13_batch* b) {
     if (!b) return 0;
     long long n = 0;
@@ -885,6 +914,8 @@ int lbm13_autotune(lbm13_ctx* c, int steps, int* tile_x, int* tile_y) {
 }
 
 int lbm13_use_graph(lbm13_ctx* c, int k) { return c ? lbm13_batch_use_graph(c->b, k) : LBM13_EINVAL; }
+
+int lbm13_launch_config(const lbm13_ctx* c, int cfg[5]) { return c ? lbm13_batch_launch_config(c->b, cfg) : LBM13_EINVAL; }
 
 int lbm13_set_fused_tile(lbm13_ctx* c, int tile_x, int tile_y) {
     return c ? lbm13_batch_set_fused_tile(c->b, tile_x, tile_y) : LBM13_EINVAL;

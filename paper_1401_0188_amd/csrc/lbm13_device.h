@@ -70,7 +70,7 @@ template <typename R>
 struct Fused;
 template <>
 struct Fused<float> {
-    static constexpr int TW = 64, TH = 12;
+    static constexpr int TW = 32, TH = 16;
 };
 template <>
 struct Fused<double> {

@@ -97,6 +97,7 @@ def lib():
         "lbm13_use_graph": (i32, [vp, i32]),
         "lbm13_set_steps_per_launch": (i32, [vp, i32]),
         "lbm13_set_fused_tile": (i32, [vp, i32, i32]),
+        "lbm13_launch_config": (i32, [vp, ip]),
         "lbm13_destroy": (i32, [vp]),
         "lbm13_last_error": (ctypes.c_char_p, [vp]),
         "lbm13_batch_workspace_bytes": (sz, [i32, ip, ip, i32]),
@@ -116,6 +117,7 @@ def lib():
         "lbm13_batch_use_graph": (i32, [vp, i32]),
         "lbm13_batch_set_steps_per_launch": (i32, [vp, i32]),
         "lbm13_batch_set_fused_tile": (i32, [vp, i32, i32]),
+        "lbm13_batch_launch_config": (i32, [vp, ip]),
         "lbm13_batch_nodes": (i64, [vp]),
         "lbm13_batch_destroy": (i32, [vp]),
         "lbm13_batch_last_error": (ctypes.c_char_p, [vp]),
@@ -178,6 +180,12 @@ def _dev_f64(a, torch, n):
 
 class _Base:
     _prefix = ""
+
+    def launch_config(self) -> dict:
+        """{steps_per_launch, tile (single-step), fused_tile (two-step)}."""
+        cfg = (ctypes.c_int * 5)()
+        self._check(getattr(lib(), self._prefix + "launch_config")(self._h, cfg))
+        return dict(steps_per_launch=cfg[0], tile=(cfg[1], cfg[2]), fused_tile=(cfg[3], cfg[4]))
 
     def _check(self, st):
         if st != OK:

@@ -45,13 +45,15 @@ def params_pair(**kw):
 
 
 def run_both(nx, ny, fields, steps, kinds=(0, 0, 0, 0), u_t=(0, 0, 0, 0), T_w=(0, 0, 0, 0),
-             precision=0, tile=None, spl=1, graph=0, **kw):
+             precision=0, tile=None, spl=1, graph=0, fused_tile=None, **kw):
     lbm13 = _lb()
     po, pl = params_pair(**kw)
     so = oracle.sides(kinds, u_t, T_w)
     lat = lbm13.Lattice(nx, ny, precision)
     if tile:
         lat.set_tile(*tile)
+    if fused_tile:
+        lat.set_fused_tile(*fused_tile)
     if spl != 1:
         lat.set_steps_per_launch(spl)
     if graph:
@@ -193,10 +195,11 @@ def test_full_size_4096_matches_oracle(precision):
     """The 4096^2 periodic shear + acoustic wave at full size, a few steps, in
     the tile shape the benchmark uses."""
     lbm13 = _lb()
-    from bench import BENCH_TILE
-    say("full size 4096^2 precision %d, 3 steps, tile %s" % (precision, BENCH_TILE))
-    lat, gs, gm, fs, om, *_ = run_both(4096, 4096, workloads.shear_acoustic(4096), 3, precision=precision,
-                                       tile=BENCH_TILE)
+    from bench import BENCH_CONFIG
+    cfg = BENCH_CONFIG[precision]
+    say("full size 4096^2 precision %d, 4 steps, config %s" % (precision, cfg))
+    lat, gs, gm, fs, om, *_ = run_both(4096, 4096, workloads.shear_acoustic(4096), 4, precision=precision,
+                                       tile=cfg["tile"], spl=cfg["spl"], fused_tile=cfg["fused_tile"])
     if precision == 0:
         assert_fp64(gs, gm, fs, om)
     else:
@@ -506,6 +509,7 @@ def test_two_steps_per_launch_batched_full_size(workload):
     steps = 200
     say("two-step %s full batch, %d steps" % (workload, steps))
     b = bench.build_batch(specs, lbm13.FP32_DEV)
+    b.set_fused_tile(32, 8)
     b.set_steps_per_launch(2)
     b.use_graph(50)
     b.step(steps)
@@ -515,3 +519,35 @@ def test_two_steps_per_launch_batched_full_size(workload):
         om = _oracle_for_spec(specs[i], steps)
         gm = [t.cpu().numpy() for t in b.moments(i)]
         assert_fp32(gm, om)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_two_step_tile_shape(precision):
+    lbm13 = _lb()
+    nx, ny, kinds, u_t, T_w, extra, steps = WALL_CASES["closed_moving_adiabatic"]
+    fields = workloads.cavity_fields(nx, ny=ny, seed=31)
+    for ft in lbm13.FUSED_TILE_SHAPES[precision]:
+        say("two-step tile %s precision %d" % (ft, precision))
+        lat, gs, gm, fs, om, *_ = run_both(nx, ny, fields, 60, kinds, u_t, T_w, precision=precision, spl=2,
+                                           fused_tile=ft, **extra)
+        if precision == 0:
+            assert_fp64(gs, gm, fs, om)
+        else:
+            assert_fp32(gm, om)
+
+
+def test_autotune_considers_two_step_launches():
+    lbm13 = _lb()
+    say("autotune with two-step candidates")
+    fields = workloads.shear_acoustic(512)
+    lat = lbm13.Lattice(512, 512, lbm13.FP32_DEV)
+    lat.set_params()
+    lat.init_moments(*fields)
+    lat.autotune(6)
+    cfg = lat.launch_config()
+    assert cfg["steps_per_launch"] in (1, 2)
+    n = lat.steps_done()
+    lat.step(7)
+    po = oracle.params()
+    f = oracle.run(oracle.init(*fields, po), po, oracle.sides(), n + 7)
+    assert_fp32([t.cpu().numpy() for t in lat.moments()], oracle.moments(f, po))
