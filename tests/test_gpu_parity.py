@@ -366,7 +366,11 @@ def test_autotune_keeps_results():
     lat.set_params(sides=sides)
     lat.init_moments(*fields)
     tx, ty = lat.autotune(4)
-    assert (tx, ty) in lbm13.TILE_SHAPES
+    cfg = lat.launch_config()
+    if cfg["steps_per_launch"] == 1:
+        assert (tx, ty) == cfg["tile"] and (tx, ty) in lbm13.TILE_SHAPES
+    else:
+        assert (tx, ty) == cfg["fused_tile"] and (tx, ty) in lbm13.FUSED_TILE_SHAPES[lbm13.FP64]
     n = lat.steps_done()
     po = oracle.params()
     f = oracle.run(oracle.init(*fields, po), po, oracle.sides((2, 2, 1, 1), (0, 0, 0, 0), (-1.995, -2.005, 0, 0)), n)
