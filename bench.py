@@ -26,8 +26,8 @@ sys.path.insert(0, ROOT)
 # Launch configuration timed here: two time steps per launch (tile + halo in
 # LDS), with the two-step tile of each precision; the single-step tile is used
 # for the plain single-step FP64 comparison.
-BENCH_CONFIG = {1: dict(spl=2, fused_tile=(32, 16), tile=(64, 8)),
-                0: dict(spl=2, fused_tile=(32, 8), tile=(64, 8))}
+BENCH_CONFIG = {1: dict(spl=2, fused_tile=(32, 32), tile=(64, 8)),
+                0: dict(spl=2, fused_tile=(32, 16), tile=(64, 8))}
 BENCH_TILE = BENCH_CONFIG[1]["tile"]
 GRAPH_K = 100                 # steps per captured HIP graph
 BYTES_PER_LU = {0: 208, 1: 104}  # 13 loads + 13 stores of populations, FP64 / FP32
@@ -175,6 +175,7 @@ def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=Tru
         b = build_batch(specs, precision)  # fresh state after tuning
         b.set_tile(*cfg["tile"])
         b.set_fused_tile(*cfg["fused_tile"])
+        b.set_interior_kernel(cfg["interior_kernel"])
         b.set_steps_per_launch(cfg["steps_per_launch"])
     if graph_k:
         b.use_graph(graph_k)

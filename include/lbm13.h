@@ -175,16 +175,18 @@ long long lbm13_steps_done(const lbm13_ctx *ctx);
  * for unsupported shapes. */
 int lbm13_set_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
 
-/* Time every supported launch configuration (single-step tile shapes and
- * two-steps-per-launch tile shapes) for `steps` steps on the current state
+/* Time every supported launch configuration (single-step tile shapes,
+ * two-steps-per-launch tile shapes with and without the interior kernel) for
+ * `steps` steps on the current state
  * (the state is advanced, so save it first if needed) and keep the fastest.
  * Writes the chosen kernel's tile shape to tile_x/tile_y when not NULL (see
  * lbm13_launch_config for the whole choice).  Synchronises. */
 int lbm13_autotune(lbm13_ctx *ctx, int steps, int *tile_x, int *tile_y);
 
 /* Current launch configuration: cfg = {steps per launch, single-step tile_x,
- * tile_y, two-step tile_x, tile_y}.  Host-only. */
-int lbm13_launch_config(const lbm13_ctx *ctx, int cfg[5]);
+ * tile_y, two-step tile_x, tile_y, interior kernel on (1) or off (0)}.
+ * Host-only. */
+int lbm13_launch_config(const lbm13_ctx *ctx, int cfg[6]);
 
 /* Capture k steps (k even, 2..4096) into a HIP graph that lbm13_step() then
  * replays for every full block of k steps; k = 0 switches graphs off. */
@@ -197,11 +199,20 @@ int lbm13_use_graph(lbm13_ctx *ctx, int k);
  * done by a single-step launch.  EINVAL for other values. */
 int lbm13_set_steps_per_launch(lbm13_ctx *ctx, int k);
 
-/* Tile of the two-steps-per-launch kernel: (64, 12), (64, 8), (64, 4),
- * (32, 16), (32, 8) or (32, 4) nodes, of which FP64 accepts the shapes whose
- * region (tile + 2-node halo) x 13 populations fits 64 KB of LDS: (64, 4),
- * (32, 8), (32, 4).  Defaults: (32, 16) FP32, (32, 8) FP64.  EINVAL otherwise. */
+/* Tile of the two-steps-per-launch kernels: (64, 16), (64, 12), (64, 8),
+ * (64, 4), (32, 32), (32, 16), (32, 8) or (32, 4) nodes, both precisions.
+ * Tiles whose region (tile + 2-node halo) and its sources lie inside the domain
+ * away from walls and wraps run a kernel that keeps only 13 x tile values in
+ * LDS; the others keep the region (up to 141 KB, FP64 64 x 16).
+ * Defaults: (32, 32) FP32, (32, 16) FP64.  EINVAL otherwise. */
 int lbm13_set_fused_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
+
+/* Two-step launches: 1 (default) runs the tiles whose region lies inside the
+ * domain away from walls and wraps on a separate kernel that keeps 13 x tile
+ * values in LDS, concurrently with the general kernel on the other tiles;
+ * 0 runs every tile on the general kernel (fewer, better balanced workgroups
+ * for batches of small domains).  Results are identical.  EINVAL otherwise. */
+int lbm13_set_interior_kernel(lbm13_ctx *ctx, int on);
 
 /* Destroy the context (frees host objects and graphs; never the workspace). */
 int lbm13_destroy(lbm13_ctx *ctx);
@@ -238,7 +249,8 @@ int lbm13_batch_autotune(lbm13_batch *b, int steps, int *tile_x, int *tile_y);
 int lbm13_batch_use_graph(lbm13_batch *b, int k);
 int lbm13_batch_set_steps_per_launch(lbm13_batch *b, int k);
 int lbm13_batch_set_fused_tile(lbm13_batch *b, int tile_x, int tile_y);
-int lbm13_batch_launch_config(const lbm13_batch *b, int cfg[5]);
+int lbm13_batch_set_interior_kernel(lbm13_batch *b, int on);
+int lbm13_batch_launch_config(const lbm13_batch *b, int cfg[6]);
 long long lbm13_batch_nodes(const lbm13_batch *b);
 int lbm13_batch_destroy(lbm13_batch *b);
 const char *lbm13_batch_last_error(const lbm13_batch *b);

@@ -29,7 +29,7 @@ hipError_t launch_step(int, int, const R*, R*, const Dom<R>*, const Tile*, int, 
 template <typename R>
 hipError_t launch_side_fill(const R*, const Dom<R>*, const WallLine*, int, R*, int, int, hipStream_t);
 template <typename R>
-hipError_t launch_step2(int, int, const R*, R*, const Dom<R>*, const Tile*, int, R*, int, hipStream_t);
+hipError_t launch_step2(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int, hipStream_t);
 template <typename R>
 hipError_t launch_diag(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, double*, hipStream_t);
 template <typename R>
@@ -52,12 +52,13 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kCoef = 16;  // doubles of init coefficients per domain
 const int kShapes[][2] = {{64, 4}, {64, 8}, {64, 16}, {32, 8}, {32, 16}};
-// fused (two steps per launch) tile shapes; FP64 only those whose region fits LDS
-const int kFusedShapes[][2] = {{64, 12}, {64, 8}, {64, 4}, {32, 16}, {32, 8}, {32, 4}};
+// fused (two steps per launch) tile shapes, as compiled in the kernels
+const int kFusedShapes[][2] = {{64, 16}, {64, 12}, {64, 8}, {64, 4}, {32, 32}, {32, 16}, {32, 8}, {32, 4}};
 
+// whether the region of a two-step tile fits the LDS of one workgroup
 bool fused_fits(int precision, int tw, int th) {
     const int es = precision == LBM13_FP64 ? 8 : 4;
-    return 13 * (tw + 4) * (th + 4) * es + 6 * (tw + th + 8) * es <= 65536;
+    return 13 * (tw + 4) * (th + 4) * es + 6 * (tw + th + 8) * es <= 163840;
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -181,6 +182,10 @@ struct lbm13_batch {
     char* ws = nullptr;
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
+    // two-step launches run the edge-tile kernel on `aux`, forked from and
+    // joined back to the launch stream, concurrently with the interior kernel
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<unsigned char> dom_host;  // staging of the Dom array
     std::vector<double> coef_host;
     std::vector<int> sides_kind;          // 4 per domain
@@ -190,6 +195,8 @@ struct lbm13_batch {
     int spl = 1;                          // time steps per launch (1 or 2)
     int ftw = 64, fth = 12;               // fused tile shape
     int nbulk = 0, nedge = 0;
+    int nfint = 0, nfedge = 0;            // interior / edge tiles of the fused table
+    int split = 1;                        // 1: interior tiles run the compact-LDS kernel
     int tile_x = 64, tile_y = 8;
     int cur = 0;                          // buffer holding the current state
     long long steps = 0;
@@ -282,9 +289,24 @@ int rebuild(lbm13_batch* b) {
     b->run = bulk;
     b->run.insert(b->run.end(), edge.begin(), edge.end());
     b->fused.clear();
-    for (int d = 0; d < b->count; ++d)
+    std::vector<Tile> fedge;
+    const long long es = b->precision == LBM13_FP64 ? 8 : 4;
+    for (int d = 0; d < b->count; ++d) {
+        // interior tiles address the 13 planes with 32-bit byte offsets
+        const bool small = b->split && (13LL * b->L.plane[d] + 2LL * b->L.pitch[d] + 2) * es <= (long long)INT32_MAX;
         for (int y0 = 0; y0 < b->ny[d]; y0 += b->fth)
-            for (int x0 = 0; x0 < b->nx[d]; x0 += b->ftw) b->fused.push_back(Tile{d, x0, y0, 0});
+            for (int x0 = 0; x0 < b->nx[d]; x0 += b->ftw) {
+                // flag 2: interior tile (region plus its gather reach inside the
+                // domain and at least two nodes from every wall, no wrap)
+                const bool in = small && x0 >= 4 && x0 + b->ftw + 4 <= b->nx[d] && y0 >= 4 &&
+                                y0 + b->fth + 4 <= b->ny[d];
+                if (in) b->fused.push_back(Tile{d, x0, y0, 2});
+                else fedge.push_back(Tile{d, x0, y0, 0});
+            }
+    }
+    b->nfint = (int)b->fused.size();
+    b->nfedge = (int)fedge.size();
+    b->fused.insert(b->fused.end(), fedge.begin(), fedge.end());
     if ((int)b->fused.size() > b->L.tfmax) return fail(b, LBM13_EINVAL, "fused tile table overflow");
     b->lines.clear();
     for (int d = 0; d < b->count; ++d) {
@@ -373,6 +395,22 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
     D->F0y_d = F0y;
     D->gx_d = p->g[0];
     D->gy_d = p->g[1];
+    const double ke = p->s_eps / 42196.0, kv = p->s_varpi / 548.0;
+    D->ke = R(ke);
+    D->ker = R(-ke * dv->c_eps_rho);
+    D->keE = R(-ke * p->c_epsE);
+    D->kv = R(kv);
+    D->kvr = R(-kv * p->c_varpi_rho);
+    D->kvE = R(-kv * p->c_varpi_E);
+    D->kX = R(p->s_XX / 68.0);
+    D->kY = R(p->s_XX / 4.0);
+    D->kXe = R(p->s_XXe / 68.0);
+    D->kq = R(dv->s_q / 20.0);
+    D->kr = R(p->s_rx / 70.0);
+    D->fjx = R(-F0x / 14.0);
+    D->fjy = R(-F0y / 14.0);
+    D->gjx = R(-p->g[0] / 14.0);
+    D->gjy = R(-p->g[1] / 14.0);
     D->qE = R(p->Q_E / 4004.0);
     D->QE = R(p->Q_E);
     D->QE_d = p->Q_E;
@@ -402,12 +440,39 @@ hipError_t launch_one_step(lbm13_batch* b, int from, hipStream_t s) {
                                  b->nbulk, run + b->nbulk, b->nedge, side, from, s);
 }
 
+// Streams and events of the concurrent two-step launch (created once, at the
+// first two-step launch or capture, never while a capture is open).
+hipError_t ensure_aux(lbm13_batch* b) {
+    hipError_t e = hipSuccess;
+    if (!b->aux) e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
+    if (e == hipSuccess && !b->ev_fork) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess && !b->ev_join) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+    return e;
+}
+
+// Two time steps: the interior tiles on stream s and, concurrently, the edge
+// tiles on the auxiliary stream (fork and join through events, which a graph
+// capture records as two parallel branches).  Both kernels read the same
+// state and write disjoint nodes; only edge tiles write wall-layer values.
 template <typename R>
 hipError_t launch_two_steps(lbm13_batch* b, int from, hipStream_t s) {
     const Tile* tiles = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_fused);
     R* side = reinterpret_cast<R*>(b->ws + b->L.wall);
-    return lbm13::launch_step2<R>(b->ftw, b->fth, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), tiles,
-                                  (int)b->fused.size(), side, from, s);
+    const R* src = buf<R>(b, from);
+    R* dst = buf<R>(b, 1 - from);
+    if (b->nfint == 0 || b->nfedge == 0 || !b->aux)
+        return lbm13::launch_step2<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->nfint, b->nfedge, side,
+                                      from, s);
+    hipError_t e = hipEventRecord(b->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->aux, b->ev_fork, 0);
+    if (e == hipSuccess)
+        e = lbm13::launch_step2<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles + b->nfint, 0, b->nfedge, side,
+                                   from, b->aux);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->aux);
+    if (e == hipSuccess)
+        e = lbm13::launch_step2<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->nfint, 0, side, from, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join, 0);
+    return e;
 }
 
 // Wall-layer side values of the kept state (after init, set_state, load).
@@ -438,6 +503,7 @@ int capture_graph(lbm13_batch* b, int parity) {
         e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(b, e, "create capture stream");
     }
+    if (b->spl == 2 && (e = ensure_aux(b)) != hipSuccess) return hip_fail(b, e, "create auxiliary stream");
     e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(b, e, "begin capture");
     int from = parity;
@@ -479,6 +545,10 @@ int step_impl(lbm13_batch* b, long long n) {
         n -= b->graph_k;
         b->steps += b->graph_k;
     }
+    if (b->spl == 2 && n >= 2) {
+        hipError_t e = ensure_aux(b);
+        if (e != hipSuccess) return hip_fail(b, e, "create auxiliary stream");
+    }
     while (b->spl == 2 && n >= 2) {
         hipError_t e = launch_two_steps<R>(b, b->cur, b->stream);
         if (e != hipSuccess) return hip_fail(b, e, "two-step launch");
@@ -513,17 +583,19 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
     b->graph_k = 0;
     steps += steps & 1;  // an even count keeps two-step launches whole
     struct Cand {
-        int spl, w, h;
+        int spl, w, h, split;
     };
     std::vector<Cand> cands;
-    for (auto& s : kShapes) cands.push_back(Cand{1, s[0], s[1]});
+    for (auto& s : kShapes) cands.push_back(Cand{1, s[0], s[1], b->split});
     for (auto& f : kFusedShapes)
-        if (fused_fits(b->precision, f[0], f[1])) cands.push_back(Cand{2, f[0], f[1]});
+        if (fused_fits(b->precision, f[0], f[1]))
+            for (int sp = 1; sp >= 0; --sp) cands.push_back(Cand{2, f[0], f[1], sp});
     float best = 1e30f;
-    Cand pick{b->spl, b->spl == 2 ? b->ftw : b->tile_x, b->spl == 2 ? b->fth : b->tile_y};
+    Cand pick{b->spl, b->spl == 2 ? b->ftw : b->tile_x, b->spl == 2 ? b->fth : b->tile_y, b->split};
     int st = LBM13_OK;
     for (const Cand& c : cands) {
         b->spl = c.spl;
+        b->split = c.split;
         if (c.spl == 1) {
             b->tile_x = c.w;
             b->tile_y = c.h;
@@ -550,6 +622,7 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->spl = pick.spl;
+    b->split = pick.split;
     if (pick.spl == 1) {
         b->tile_x = pick.w;
         b->tile_y = pick.h;
@@ -827,13 +900,21 @@ int lbm13_batch_set_steps_per_launch(lbm13_batch* b, int k) {
     return LBM13_OK;
 }
 
-int lbm13_batch_launch_config(const lbm13_batch* b, int cfg[5]) {
+int lbm13_batch_set_interior_kernel(lbm13_batch* b, int on) {
+    if (!b) return LBM13_EINVAL;
+    if (on != 0 && on != 1) return fail(b, LBM13_EINVAL, "interior kernel switch must be 0 or 1");
+    b->split = on;
+    return rebuild(b);
+}
+
+int lbm13_batch_launch_config(const lbm13_batch* b, int cfg[6]) {
     if (!b || !cfg) return LBM13_EINVAL;
     cfg[0] = b->spl;
     cfg[1] = b->tile_x;
     cfg[2] = b->tile_y;
     cfg[3] = b->ftw;
     cfg[4] = b->fth;
+    cfg[5] = b->split;
     return LBM13_OK;
 }
 
@@ -848,6 +929,9 @@ int lbm13_batch_destroy(lbm13_batch* b) {
     if (!b) return LBM13_EINVAL;
     drop_graphs(b);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     delete b;
     return LBM13_OK;
 }
@@ -915,7 +999,11 @@ int lbm13_autotune(lbm13_ctx* c, int steps, int* tile_x, int* tile_y) {
 
 int lbm13_use_graph(lbm13_ctx* c, int k) { return c ? lbm13_batch_use_graph(c->b, k) : LBM13_EINVAL; }
 
-int lbm13_launch_config(const lbm13_ctx* c, int cfg[5]) { return c ? lbm13_batch_launch_config(c->b, cfg) : LBM13_EINVAL; }
+int lbm13_launch_config(const lbm13_ctx* c, int cfg[6]) { return c ? lbm13_batch_launch_config(c->b, cfg) : LBM13_EINVAL; }
+
+int lbm13_set_interior_kernel(lbm13_ctx* c, int on) {
+    return c ? lbm13_batch_set_interior_kernel(c->b, on) : LBM13_EINVAL;
+}
 
 int lbm13_set_fused_tile(lbm13_ctx* c, int tile_x, int tile_y) {
     return c ? lbm13_batch_set_fused_tile(c->b, tile_x, tile_y) : LBM13_EINVAL;

@@ -37,6 +37,13 @@ struct alignas(16) Dom {
     R F0x, F0y, gx, gy;
     R qE;  // Q_E / 4004: the energy source divided by the norm of the E moment
     R QE;  // Q_E: the kept post-collision state carries E(t) + Q_E
+    // relaxation folded with the norms D_k for the collision:
+    //   s_eps (eps - eps^eq) / 42196 = ke eps + ker rho' + keE E'  (likewise kv.. for varpi),
+    //   kX = s_XX / 68, kY = s_XX / 4, kXe = s_XXe / 68, kq = s_q / 20, kr = s_r / 70,
+    //   -F / 14 = fjx + gjx rho' (and y)
+    R ke, ker, keE, kv, kvr, kvE;
+    R kX, kY, kXe, kq, kr;
+    R fjx, fjy, gjx, gjy;
     // walls: tangential velocity, E_W - E0 for temperature walls
     R wall_u[4];
     R wall_dE[4];
@@ -50,7 +57,9 @@ struct alignas(16) Dom {
 };
 
 // One tile of the tile tables: domain index, origin, flags (bit 0: tile holds
-// nodes within two nodes of a wall).
+// nodes within two nodes of a wall; bit 1, two-step tiles: the tile, its
+// two-node halo and their sources lie inside the domain, at least two nodes
+// from every wall, with no periodic wrap).
 struct alignas(16) Tile {
     int dom, x0, y0, flags;
 };
@@ -63,22 +72,23 @@ struct alignas(16) WallLine {
     int dom, w, pos, line;
 };
 
-// Tiles of the two-steps-per-launch kernel.  The region (TW + 4) x (TH + 4) x
-// 13 populations must fit the 64 KB of LDS a workgroup can address; Fused<R>
-// is the default shape, FusedFits tells which compiled shapes fit.
+// Tiles of the two-steps-per-launch kernels.  For tiles that touch a wall or a
+// periodic wrap the region (TW + 4) x (TH + 4) x 13 populations plus the
+// wall-layer side values must fit the 160 KB of LDS a gfx950 workgroup can
+// address; Fused<R> is the default shape.
 template <typename R>
 struct Fused;
 template <>
 struct Fused<float> {
-    static constexpr int TW = 32, TH = 16;
+    static constexpr int TW = 32, TH = 32;
 };
 template <>
 struct Fused<double> {
-    static constexpr int TW = 32, TH = 8;
+    static constexpr int TW = 32, TH = 16;
 };
 template <typename R, int TW, int TH>
 struct FusedFits {
-    static constexpr bool value = 13 * (TW + 4) * (TH + 4) * sizeof(R) + 6 * (TW + TH + 8) * sizeof(R) <= 65536;
+    static constexpr bool value = 13 * (TW + 4) * (TH + 4) * sizeof(R) + 6 * (TW + TH + 8) * sizeof(R) <= 163840;
 };
 
 constexpr int kDiagPartials = 10;  // per-tile partial reductions

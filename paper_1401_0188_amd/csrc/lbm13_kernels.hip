@@ -46,6 +46,17 @@ __constant__ double c_invD[13] = {1.0 / 13, 1.0 / 4004, 1.0 / 42196, 1.0 / 548, 
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// 1 / x from the hardware reciprocal: FP32 within 1 ulp; FP64 refined by two
+// Newton steps e = 1 - x y, y <- y + y e (each squares the relative error).
+__device__ __forceinline__ float reciprocal(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double reciprocal(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
 // ---------------------------------------------------------------------------
 // Collision of one node, in place on the deviations g (sec. 2):
 //   m = M g; Delta_k = s_k (m_k - m_k^eq) on the nine non-conserved moments;
@@ -76,20 +87,19 @@ __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
     const R rx = R(4) * d13 - R(3) * d57 + R(3) * d68 + d9;
     const R ry = R(4) * d24 - R(3) * d57 - R(3) * d68 + d10;
 
-    const R inv_rho = R(1) / (R(1) + rho);
+    const R inv_rho = reciprocal(R(1) + rho);
     const R fq = D.a1 + D.h1 * rho + D.k1 * E;
     const R fr = D.a2 + D.h2 * rho + D.k2 * E;
     // Delta_k / D_k for the even non-conserved moments
-    const R aeps = D.s_eps * (eps - (D.c_er * rho + D.c_eE * E)) * R(1.0 / 42196.0);
-    const R avp = D.s_vp * (vp - (D.c_vr * rho + D.c_vE * E)) * R(1.0 / 548.0);
-    const R aXX = D.s_XX * (XX - (jx * jx - jy * jy) * inv_rho) * R(1.0 / 68.0);
-    const R aXY = D.s_XX * (XY - jx * jy * inv_rho) * R(0.25);
-    const R aXXe = D.s_XXe * XXe * R(1.0 / 68.0);
+    const R aeps = D.ke * eps + D.ker * rho + D.keE * E;
+    const R avp = D.kv * vp + D.kvr * rho + D.kvE * E;
+    const R aXX = D.kX * (XX - (jx * jx - jy * jy) * inv_rho);
+    const R aXY = D.kY * (XY - jx * jy * inv_rho);
+    const R aXXe = D.kXe * XXe;
     // odd moments: the force enters as Delta_j = -F
-    const R Fx = D.F0x + D.gx * rho, Fy = D.F0y + D.gy * rho;
-    const R bjx = -Fx * R(1.0 / 14.0), bjy = -Fy * R(1.0 / 14.0);
-    const R bqx = D.s_q * (qx - jx * fq) * R(0.05), bqy = D.s_q * (qy - jy * fq) * R(0.05);
-    const R brx = D.s_r * (rx - jx * fr) * R(1.0 / 70.0), bry = D.s_r * (ry - jy * fr) * R(1.0 / 70.0);
+    const R bjx = D.fjx + D.gjx * rho, bjy = D.fjy + D.gjy * rho;
+    const R bqx = D.kq * (qx - jx * fq), bqy = D.kq * (qy - jy * fq);
+    const R brx = D.kr * (rx - jx * fr), bry = D.kr * (ry - jy * fr);
 
     // the energy source enters as Delta_E = -Q_E (sec. 9)
     const R aQ = D.qE;
@@ -496,12 +506,50 @@ __device__ __forceinline__ int pmod(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-template <typename R, int TW, int TH>
-__global__ __launch_bounds__(256) void step2_kernel(const R* __restrict__ src, R* __restrict__ dst,
-                                                    const Dom<R>* __restrict__ doms,
-                                                    const Tile* __restrict__ tiles, int ntiles,
-                                                    R* __restrict__ side, int from) {
-    constexpr int NT = 256, RW = TW + 4, RH = TH + 4;
+// Raw buffer access: a descriptor (uniform base address, byte range) plus a
+// 32-bit per-lane byte offset and a uniform byte offset, so a gather of 13
+// planes costs no per-lane address arithmetic.  Out-of-range loads return 0 and
+// out-of-range stores are dropped.  The descriptor's fourth word selects the
+// 32-bit data format of untyped CDNA buffer accesses.
+constexpr int kBufferWord3 = 0x00020000;
+
+template <typename R>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const R* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(base), (short)0, (int)bytes, kBufferWord3);
+}
+
+template <typename R>
+__device__ __forceinline__ R buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// Non-temporal store (cache policy bit 1).
+template <typename R>
+__device__ __forceinline__ void buffer_store_nt(R v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ void buffer_store_nt<float>(float v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                       unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 2);
+}
+template <>
+__device__ __forceinline__ void buffer_store_nt<double>(double v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                        unsigned soff) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
+}
+
+template <typename R, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void step2_kernel(const R* __restrict__ src, R* __restrict__ dst,
+                                                   const Dom<R>* __restrict__ doms,
+                                                   const Tile* __restrict__ tiles, int ntiles,
+                                                   R* __restrict__ side, int from) {
+    constexpr int RW = TW + 4, RH = TH + 4, NI = (RW * RH + NT - 1) / NT;
     __shared__ R lds[13 * RH * RW];
     __shared__ R xs[2 * RH * 3];
     __shared__ R ys[2 * RW * 3];
@@ -511,32 +559,50 @@ __global__ __launch_bounds__(256) void step2_kernel(const R* __restrict__ src, R
     const R* __restrict__ a = src + D.off;
     R* __restrict__ o = dst + D.off;
     const int ox = tl.x0 - 2, oy = tl.y0 - 2;
-    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int tid = threadIdx.x;
 
+    // Phase 1: all gathers of a thread's region nodes are issued before the
+    // first collision.  Region nodes beyond a wall (or past the region's end)
+    // gather from a clamped in-domain node and store nothing.
     const GlobalSrc<R> G{a, D.plane, D.pitch, D.nx, D.ny, D.xper, D.yper};
     const GlobalSide<R> GS{side, from};
-    for (int r = tid; r < RW * RH; r += NT) {
-        const int lx = r % RW, ly = r / RW;
-        int X = ox + lx, Y = oy + ly;
+    R g[NI][13];
+    int Xs[NI], Ys[NI];
+    bool valid[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int r = min(tid + k * NT, RW * RH - 1);
+        int X = ox + r % RW, Y = oy + r / RW;
+        bool v = tid + k * NT < RW * RH;
         // a region wraps at most once around an axis at least as long as itself
         if (D.xper) X = D.nx >= RW ? wrap(X, D.nx) : pmod(X, D.nx);
-        else if (X < 0 || X >= D.nx) continue;
+        else { v = v && X >= 0 && X < D.nx; X = min(max(X, 0), D.nx - 1); }
         if (D.yper) Y = D.ny >= RH ? wrap(Y, D.ny) : pmod(Y, D.ny);
-        else if (Y < 0 || Y >= D.ny) continue;
-        R g[13];
+        else { v = v && Y >= 0 && Y < D.ny; Y = min(max(Y, 0), D.ny - 1); }
+        Xs[k] = X;
+        Ys[k] = Y;
+        valid[k] = v;
         const bool xw = !D.xper && (X < 2 || X >= D.nx - 2);
         const bool yw = !D.yper && (Y < 2 || Y >= D.ny - 2);
-        if (xw || yw) gather_wall(G, GS, D, X, Y, g);
-        else gather_bulk(a, D, X, Y, g);
-        if (D.collide) collide(g, D);
+        if (xw || yw) gather_wall(G, GS, D, X, Y, g[k]);
+        else gather_bulk(a, D, X, Y, g[k]);
+    }
 #pragma unroll
-        for (int i = 0; i < 13; ++i) lds[(i * RH + ly) * RW + lx] = g[i];
+    for (int k = 0; k < NI; ++k) {
+        if (!valid[k]) continue;
+        const int r = tid + k * NT, lx = r % RW, ly = r / RW;
+        const int X = Xs[k], Y = Ys[k];
+        if (D.collide) collide(g[k], D);
+#pragma unroll
+        for (int i = 0; i < 13; ++i) lds[(i * RH + ly) * RW + lx] = g[k][i];
+        const bool xw = !D.xper && (X < 2 || X >= D.nx - 2);
+        const bool yw = !D.yper && (Y < 2 || Y >= D.ny - 2);
         if (xw || yw) {
             R rho = R(0), E = -D.QE;
 #pragma unroll
             for (int i = 0; i < 13; ++i) {
-                rho += g[i];
-                E += R(c_M[1][i]) * g[i];
+                rho += g[k][i];
+                E += R(c_M[1][i]) * g[k][i];
             }
             if (xw) {
                 if (X == 0) { xs[(0 * RH + ly) * 3 + 0] = rho; xs[(0 * RH + ly) * 3 + 1] = E; }
@@ -571,6 +637,98 @@ __global__ __launch_bounds__(256) void step2_kernel(const R* __restrict__ src, R
         if (D.collide) collide(g, D);
         store_node(o, D.plane, Y * D.pitch + X, g);
         if (near) record_wall_layers(side, D, 1 - from, X, Y, g);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per launch on interior tiles (tile flag 2: the tile, its two-node
+// halo and every source of their gathers lie inside the domain, at least two
+// nodes from any wall, with no wrap).  Phase 2 reads population i of the
+// intermediate state only over the tile shifted back by v_i, so LDS keeps
+// TW x TH values per population instead of the whole (TW + 4)(TH + 4) region
+// and more workgroups share a CU.  Same per-node arithmetic as step2_kernel.
+template <int I>
+struct Slot {  // LDS slot of population I: velocity 10, (0, 2), takes slot 0
+    static constexpr int value = (I + 3) % 13;
+};
+
+template <typename R, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void step2_interior_kernel(const R* __restrict__ src, R* __restrict__ dst,
+                                                           const Dom<R>* __restrict__ doms,
+                                                           const Tile* __restrict__ tiles, int ntiles) {
+    constexpr int RW = TW + 4, RH = TH + 4, N = TW * TH;
+    constexpr int NI = (RW * RH + NT - 1) / NT;
+    // population i of region node (lx, ly) sits at kLead + slot(i) N + (ly - 2 + vy_i) TW + lx - 2 + vx_i;
+    // kLead keeps that index non-negative for the population in slot 0
+    constexpr int kLead = 2;
+    __shared__ R lds[kLead + 13 * N];
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const Tile tl = tiles[t];
+    const Dom<R>& D = doms[tl.dom];
+    const R* __restrict__ a = src + D.off;
+    R* __restrict__ o = dst + D.off;
+    const int P = D.pitch, S = D.plane;
+    const int tid = threadIdx.x;
+
+    // Phase 1: every region node a thread owns is requested before the first
+    // collision, so the memory latencies overlap (a thread past the region's
+    // end re-reads its last node and stores nothing).  The 13 planes are read
+    // through one descriptor based two rows and two columns before plane 0, so
+    // every per-velocity offset is non-negative (interior tiles exist only in
+    // domains whose planes span less than 2^31 bytes).
+    constexpr int es = (int)sizeof(R);
+    const __amdgpu_buffer_rsrc_t in = buffer_rsrc(a - (2 * P + 2), (unsigned)((13 * S + 2 * P + 2) * es));
+    R g[NI][13];
+    int lxs[NI], lys[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int r = min(tid + k * NT, RW * RH - 1);
+        lxs[k] = r % RW;
+        lys[k] = r / RW;
+        const unsigned c = (unsigned)(((tl.y0 - 2 + lys[k]) * P + tl.x0 - 2 + lxs[k]) * es);
+#pragma unroll
+        for (int i = 0; i < 13; ++i)
+            g[k][i] = buffer_load<R>(in, c, (unsigned)((i * S + (2 - kVY[i]) * P + 2 - kVX[i]) * es));
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        if (D.collide) collide(g[k], D);
+        if (tid + k * NT < RW * RH) {
+            const int lx = lxs[k], ly = lys[k], base = ly * TW + lx;
+#define LBM13_WINDOW_STORE(I)                                                                              \
+    if ((unsigned)(lx - 2 + kVX[I]) < (unsigned)TW && (unsigned)(ly - 2 + kVY[I]) < (unsigned)TH)          \
+        lds[base + (kLead + Slot<I>::value * N + (kVY[I] - 2) * TW + kVX[I] - 2)] = g[k][I];
+            LBM13_WINDOW_STORE(0) LBM13_WINDOW_STORE(1) LBM13_WINDOW_STORE(2) LBM13_WINDOW_STORE(3)
+            LBM13_WINDOW_STORE(4) LBM13_WINDOW_STORE(5) LBM13_WINDOW_STORE(6) LBM13_WINDOW_STORE(7)
+            LBM13_WINDOW_STORE(8) LBM13_WINDOW_STORE(9) LBM13_WINDOW_STORE(10) LBM13_WINDOW_STORE(11)
+            LBM13_WINDOW_STORE(12)
+#undef LBM13_WINDOW_STORE
+        }
+    }
+    __syncthreads();
+
+    // Phase 2: tile node r reads every population at index r of its slot.
+    const __amdgpu_buffer_rsrc_t out = buffer_rsrc(o, (unsigned)(13 * S * es));
+    for (int r = tid; r < N; r += NT) {
+        const int tx = r % TW, ty = r / TW;
+        const unsigned c = (unsigned)(((tl.y0 + ty) * P + tl.x0 + tx) * es);
+        R h[13];
+        h[0] = lds[kLead + Slot<0>::value * N + r];
+        h[1] = lds[kLead + Slot<1>::value * N + r];
+        h[2] = lds[kLead + Slot<2>::value * N + r];
+        h[3] = lds[kLead + Slot<3>::value * N + r];
+        h[4] = lds[kLead + Slot<4>::value * N + r];
+        h[5] = lds[kLead + Slot<5>::value * N + r];
+        h[6] = lds[kLead + Slot<6>::value * N + r];
+        h[7] = lds[kLead + Slot<7>::value * N + r];
+        h[8] = lds[kLead + Slot<8>::value * N + r];
+        h[9] = lds[kLead + Slot<9>::value * N + r];
+        h[10] = lds[kLead + Slot<10>::value * N + r];
+        h[11] = lds[kLead + Slot<11>::value * N + r];
+        h[12] = lds[kLead + Slot<12>::value * N + r];
+        if (D.collide) collide(h, D);
+#pragma unroll
+        for (int i = 0; i < 13; ++i) buffer_store_nt<R>(h[i], out, c, (unsigned)(i * S * es));
     }
 }
 
@@ -888,20 +1046,25 @@ hipError_t launch_diag(int tile_x, int tile_y, const R* src, const Dom<R>* doms,
     return hipGetLastError();
 }
 
+// Two steps per launch: interior tiles tiles[0, nint), then tiles touching a
+// wall or a periodic wrap tiles[nint, nint + nedge).
 template <typename R>
-hipError_t launch_step2(int tw, int th, const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int ntiles,
-                        R* side, int from, hipStream_t s) {
-    if (ntiles <= 0) return hipSuccess;
-    const dim3 blk(64, 4);
-#define LBM13_FUSED(TW, TH)                                                                        \
-    if (tw == TW && th == TH && FusedFits<R, TW, TH>::value) {                                     \
-        step2_kernel<R, TW, (FusedFits<R, TW, TH>::value ? TH : 1)><<<ntiles, blk, 0, s>>>(       \
-            src, dst, doms, tiles, ntiles, side, from);                                            \
-        return hipGetLastError();                                                                  \
+hipError_t launch_step2(int tw, int th, const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int nint,
+                        int nedge, R* side, int from, hipStream_t s) {
+#define LBM13_FUSED(TW, TH)                                                                                    \
+    if (tw == TW && th == TH) {                                                                                \
+        static_assert(FusedFits<R, TW, TH>::value, "two-step region exceeds LDS");                             \
+        constexpr int NT = TW * TH >= 1024 ? 512 : 256;                                                        \
+        if (nint > 0) step2_interior_kernel<R, TW, TH, NT><<<nint, NT, 0, s>>>(src, dst, doms, tiles, nint);  \
+        if (nedge > 0)                                                                                         \
+            step2_kernel<R, TW, TH, NT><<<nedge, NT, 0, s>>>(src, dst, doms, tiles + nint, nedge, side, from); \
+        return hipGetLastError();                                                                              \
     }
+    LBM13_FUSED(64, 16)
     LBM13_FUSED(64, 12)
     LBM13_FUSED(64, 8)
     LBM13_FUSED(64, 4)
+    LBM13_FUSED(32, 32)
     LBM13_FUSED(32, 16)
     LBM13_FUSED(32, 8)
     LBM13_FUSED(32, 4)
@@ -950,7 +1113,7 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
 #define LBM13_INSTANTIATE(R)                                                                                      \
     template hipError_t launch_step<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, \
                                        R*, int, hipStream_t);                                                     \
-    template hipError_t launch_step2<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, R*, int,          \
+    template hipError_t launch_step2<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int,     \
                                         hipStream_t);                                                             \
     template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, int,          \
                                             hipStream_t);                                                         \

@@ -27,8 +27,8 @@ WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 DIAG_NAMES = ("sum_rho", "sum_jx", "sum_jy", "sum_E", "heat_flux", "Nu_mean", "u_max", "asym_abs",
               "asym_rel", "nonfinite", "rho_min")
 TILE_SHAPES = ((64, 4), (64, 8), (64, 16), (32, 8), (32, 16))
-FUSED_TILE_SHAPES = {FP32_DEV: ((64, 12), (64, 8), (64, 4), (32, 16), (32, 8), (32, 4)),
-                     FP64: ((64, 4), (32, 8), (32, 4))}
+_FUSED = ((64, 16), (64, 12), (64, 8), (64, 4), (32, 32), (32, 16), (32, 8), (32, 4))
+FUSED_TILE_SHAPES = {FP32_DEV: _FUSED, FP64: _FUSED}
 
 
 class LBM13Error(RuntimeError):
@@ -97,6 +97,7 @@ def lib():
         "lbm13_use_graph": (i32, [vp, i32]),
         "lbm13_set_steps_per_launch": (i32, [vp, i32]),
         "lbm13_set_fused_tile": (i32, [vp, i32, i32]),
+        "lbm13_set_interior_kernel": (i32, [vp, i32]),
         "lbm13_launch_config": (i32, [vp, ip]),
         "lbm13_destroy": (i32, [vp]),
         "lbm13_last_error": (ctypes.c_char_p, [vp]),
@@ -117,6 +118,7 @@ def lib():
         "lbm13_batch_use_graph": (i32, [vp, i32]),
         "lbm13_batch_set_steps_per_launch": (i32, [vp, i32]),
         "lbm13_batch_set_fused_tile": (i32, [vp, i32, i32]),
+        "lbm13_batch_set_interior_kernel": (i32, [vp, i32]),
         "lbm13_batch_launch_config": (i32, [vp, ip]),
         "lbm13_batch_nodes": (i64, [vp]),
         "lbm13_batch_destroy": (i32, [vp]),
@@ -182,10 +184,15 @@ class _Base:
     _prefix = ""
 
     def launch_config(self) -> dict:
-        """{steps_per_launch, tile (single-step), fused_tile (two-step)}."""
-        cfg = (ctypes.c_int * 5)()
+        """{steps_per_launch, tile (single-step), fused_tile (two-step),
+        interior_kernel (two-step interior tiles on their own kernel)}."""
+        cfg = (ctypes.c_int * 6)()
         self._check(getattr(lib(), self._prefix + "launch_config")(self._h, cfg))
-        return dict(steps_per_launch=cfg[0], tile=(cfg[1], cfg[2]), fused_tile=(cfg[3], cfg[4]))
+        return dict(steps_per_launch=cfg[0], tile=(cfg[1], cfg[2]), fused_tile=(cfg[3], cfg[4]),
+                    interior_kernel=bool(cfg[5]))
+
+    def set_interior_kernel(self, on: bool):
+        self._check(getattr(lib(), self._prefix + "set_interior_kernel")(self._h, int(bool(on))))
 
     def _check(self, st):
         if st != OK:

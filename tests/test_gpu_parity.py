@@ -527,17 +527,50 @@ def test_two_steps_per_launch_batched_full_size(workload):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_every_two_step_tile_shape(precision):
+    """Every two-step tile shape: a 66 x 67 closed cavity (no interior tile)
+    and 203 x 93 domains large enough for interior tiles of every shape, with
+    ragged edge tiles, walls on y only and fully periodic."""
     lbm13 = _lb()
     nx, ny, kinds, u_t, T_w, extra, steps = WALL_CASES["closed_moving_adiabatic"]
-    fields = workloads.cavity_fields(nx, ny=ny, seed=31)
+    cases = [(nx, ny, workloads.cavity_fields(nx, ny=ny, seed=31), kinds, u_t, T_w, extra),
+             (203, 93, workloads.shear_acoustic(203, 93), (0, 0, 2, 1), (0, 0, 0.02, -0.01),
+              (0, 0, -1.99, 0), dict(g=(0.0, -1e-4))),
+             (203, 93, workloads.shear_acoustic(203, 93), (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0),
+              dict(F0=(1e-5, -2e-5)))]
     for ft in lbm13.FUSED_TILE_SHAPES[precision]:
-        say("two-step tile %s precision %d" % (ft, precision))
-        lat, gs, gm, fs, om, *_ = run_both(nx, ny, fields, 60, kinds, u_t, T_w, precision=precision, spl=2,
-                                           fused_tile=ft, **extra)
-        if precision == 0:
-            assert_fp64(gs, gm, fs, om)
-        else:
-            assert_fp32(gm, om)
+        for cnx, cny, fields, ck, cu, cT, cx in cases:
+            say("two-step tile %s precision %d, %d x %d sides %s" % (ft, precision, cnx, cny, ck))
+            lat, gs, gm, fs, om, *_ = run_both(cnx, cny, fields, 30, ck, cu, cT, precision=precision, spl=2,
+                                               fused_tile=ft, **cx)
+            if precision == 0:
+                assert_fp64(gs, gm, fs, om)
+            else:
+                assert_fp32(gm, om)
+            lat.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_interior_kernel_switch_is_bit_exact(precision):
+    """Two-step launches with the interior tiles on their own kernel (run
+    concurrently with the general kernel) and with every tile on the general
+    kernel give the same bits."""
+    lbm13 = _lb()
+    say("interior kernel on/off precision %d" % precision)
+    fields = workloads.shear_acoustic(203, 93)
+    sides = lbm13.make_sides((0, 0, 2, 1), (0, 0, 0.02, -0.01), (0, 0, -1.99, 0))
+    states = []
+    for on in (True, False):
+        lat = lbm13.Lattice(203, 93, precision)
+        lat.set_fused_tile(32, 16)
+        lat.set_steps_per_launch(2)
+        lat.set_interior_kernel(on)
+        assert lat.launch_config()["interior_kernel"] == on
+        lat.set_params(sides=sides, g=(0.0, -1e-4))
+        lat.init_moments(*fields)
+        lat.step(24)
+        states.append(lat.get_state().cpu().numpy())
+        lat.destroy()
+    assert np.array_equal(states[0], states[1])
 
 
 def test_autotune_considers_two_step_launches():
