@@ -148,9 +148,26 @@ int lbm13_moments(lbm13_ctx *ctx, double *rho, double *ux, double *uy, double *T
  *      (0 when T_W == T_E)
  *  [6] max |u|  [7] max |u(x) + u(xbar)| with xbar the node reflected through
  *      the domain centre (Fig. 14)  [8] [7]/[6]
- *  [9] count of non-finite stored values  [10] min rho  [11..15] reserved (0).
+ *  [9] count of non-finite stored values  [10] min rho
+ *  walls (sec. 7), for the exchange of the next step: an incoming link whose
+ *  source lies beyond a wall brings its bounce-back / anti-bounce-back value,
+ *  an outgoing link whose target lies beyond it takes f*; a link beyond an x
+ *  and a y wall counts for the x wall:
+ *  [11] Nu at the West wall: (energy - B mass) taken in per step, per unit
+ *       wall length, times nx / (kappa_E (T_W - T_E))  [12] the same given out
+ *       at the East wall (0 when x is periodic or T_W == T_E)
+ *  [13] energy taken in through all walls per step (sum E(t+1) - sum E(t)
+ *       - Q_E nx ny)  [14] mass taken in (sum rho(t+1) - sum rho(t); nonzero
+ *       where anti-bounce-back links let mass through)  [15] reserved (0).
  * Returns LBM13_ENONFINITE (with out filled) when [9] > 0 or [10] <= 0. */
 int lbm13_diagnostics(lbm13_ctx *ctx, double out[16]);
+
+/* Fourier projection of the current state (sec. 6 aggregates), written to the
+ * host array out[8] (synchronises): out[2q] + i out[2q+1] =
+ * sum_{x,y} q(x, y) exp(-2 pi i (kx x / nx + ky y / ny)) for q = rho, u_x,
+ * u_y, E (u and E as in lbm13_moments; E = T + (13/2)|u|^2).  Any integers
+ * kx, ky.  FP64 accumulation in a fixed order. */
+int lbm13_fourier(lbm13_ctx *ctx, int kx, int ky, double out[8]);
 
 /* Copy the kept post-collision populations f*(t) as absolute FP64 values into
  * the device array dst[13][ny][nx] (dense), or load them from src (same
@@ -249,6 +266,7 @@ int lbm13_batch_autotune(lbm13_batch *b, int steps, int *tile_x, int *tile_y);
 int lbm13_batch_use_graph(lbm13_batch *b, int k);
 int lbm13_batch_set_steps_per_launch(lbm13_batch *b, int k);
 int lbm13_batch_set_fused_tile(lbm13_batch *b, int tile_x, int tile_y);
+int lbm13_batch_fourier(lbm13_batch *b, int i, int kx, int ky, double out[8]);
 int lbm13_batch_set_interior_kernel(lbm13_batch *b, int on);
 int lbm13_batch_launch_config(const lbm13_batch *b, int cfg[6]);
 long long lbm13_batch_nodes(const lbm13_batch *b);

@@ -91,6 +91,8 @@ def lib():
         L.or13_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(Params),
                                        ctypes.POINTER(Sides), dp]
         L.or13_num_threads.restype = ctypes.c_int
+        L.or13_fourier.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(Params), ctypes.c_int,
+                                   ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -195,7 +197,8 @@ def moments(f: np.ndarray, p: Params):
 
 
 DIAG_NAMES = ("sum_rho", "sum_jx", "sum_jy", "sum_E", "heat_flux", "Nu_mean", "u_max",
-              "asym_abs", "asym_rel", "nonfinite", "rho_min")
+              "asym_abs", "asym_rel", "nonfinite", "rho_min", "Nu_west", "Nu_east", "wall_energy_in",
+              "wall_mass_in")
 
 
 def diagnostics(f: np.ndarray, p: Params, s: Sides) -> dict:
@@ -204,6 +207,15 @@ def diagnostics(f: np.ndarray, p: Params, s: Sides) -> dict:
     out = np.zeros(16)
     lib().or13_diagnostics(nx, ny, _p(f), ctypes.byref(p), ctypes.byref(s), _p(out))
     return dict(zip(DIAG_NAMES, out[:len(DIAG_NAMES)]))
+
+
+def fourier(f: np.ndarray, p: Params, kx: int, ky: int) -> dict:
+    """sum q exp(-2 pi i (kx x/nx + ky y/ny)) for q = rho, ux, uy, E (complex)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    _, ny, nx = f.shape
+    out = np.zeros(8)
+    lib().or13_fourier(nx, ny, _p(f), ctypes.byref(p), int(kx), int(ky), _p(out))
+    return {q: complex(out[2 * k], out[2 * k + 1]) for k, q in enumerate(("rho", "ux", "uy", "E"))}
 
 
 def num_threads() -> int:

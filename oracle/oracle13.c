@@ -494,6 +494,33 @@ void or13_diagnostics(int nx, int ny, const double *f, const or13_params *p, con
             double a = sqrt(ax * ax + ay * ay);
             if (a > asym) asym = a;
         }
+    /* Energy exchanged with each wall in the next step (sec. 7 walls): an
+       incoming link (x, i) whose source x - v_i lies beyond wall w brings
+       M_E,i f_i(x, t+1); an outgoing link (x, j) whose target x + v_j lies
+       beyond w takes M_E,j f*_j(x, t).  A link beyond an x wall and a y wall
+       counts for the x wall, as in the streaming. */
+    double *fn = malloc(sizeof(double) * Q * n);
+    or13_stream(nx, ny, f, fs, p, sd, fn);
+    int yper = (sd->kind[2] == OR_PERIODIC);
+    double wflux[4] = {0.0, 0.0, 0.0, 0.0}, wmass[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long c = (long)y * nx + x;
+            for (int i = 0; i < Q; ++i) {
+                for (int dir = -1; dir <= 1; dir += 2) {
+                    int sx = x + dir * VX[i], sy = y + dir * VY[i], w = -1;
+                    if (!xper && sx < 0) w = 0;
+                    else if (!xper && sx >= nx) w = 1;
+                    else if (!yper && sy < 0) w = 2;
+                    else if (!yper && sy >= ny) w = 3;
+                    if (w < 0) continue;
+                    double v = dir < 0 ? fn[i * n + c] : -fs[i * n + c];  /* incoming, outgoing */
+                    wflux[w] += Mm[M_E][i] * v;
+                    wmass[w] += v;
+                }
+            }
+        }
+    free(fn);
     double dT = sd->T_w[0] - sd->T_w[1];
     int faces = xper ? nx : (fhi - flo + 1);
     out[0] = srho;
@@ -507,7 +534,43 @@ void or13_diagnostics(int nx, int ny, const double *f, const or13_params *p, con
     out[8] = umax > 0 ? asym / umax : 0.0;
     out[9] = nonfin;
     out[10] = rmin;
+    /* wall Nusselt numbers: energy per step through the West (in) and East (out)
+       walls per unit wall length, less B times the mass exchanged (the advected
+       equilibrium part, as in the face flux), over the conduction flux kappa_E dT / nx */
+    double wscale = (!xper && dT != 0.0) ? (double)nx / (d.kappa_E * dT) / ny : 0.0;
+    out[11] = (wflux[0] - d.B * wmass[0]) * wscale;
+    out[12] = -(wflux[1] - d.B * wmass[1]) * wscale;
+    out[13] = wflux[0] + wflux[1] + wflux[2] + wflux[3];
+    out[14] = wmass[0] + wmass[1] + wmass[2] + wmass[3];
     free(rho); free(ux); free(uy); free(T); free(fs);
+}
+
+/* Fourier projection of rho, u_x, u_y and E (sec. 6 aggregates):
+   out[2q] + i out[2q+1] = sum_{x,y} q(x, y) exp(-2 pi i (kx x / nx + ky y / ny)). */
+void or13_fourier(int nx, int ny, const double *f, const or13_params *p, int kx, int ky, double *out)
+{
+    build_matrix();
+    long n = (long)nx * ny;
+    double *rho = malloc(sizeof(double) * n), *ux = malloc(sizeof(double) * n);
+    double *uy = malloc(sizeof(double) * n), *T = malloc(sizeof(double) * n);
+    or13_moments(nx, ny, f, p, rho, ux, uy, T);
+    for (int k = 0; k < 8; ++k) out[k] = 0.0;
+    const double pi = 3.14159265358979323846;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long c = (long)y * nx + x;
+            double fl[Q], m[Q];
+            for (int i = 0; i < Q; ++i) fl[i] = f[i * n + c];
+            f_to_moments(fl, m);
+            double th = 2.0 * pi * ((double)kx * x / nx + (double)ky * y / ny);
+            double cr = cos(th), ci = -sin(th);
+            double q[4] = {rho[c], ux[c], uy[c], m[M_E]};
+            for (int k = 0; k < 4; ++k) {
+                out[2 * k] += q[k] * cr;
+                out[2 * k + 1] += q[k] * ci;
+            }
+        }
+    free(rho); free(ux); free(uy); free(T);
 }
 
 int or13_num_threads(void)

@@ -31,7 +31,11 @@ hipError_t launch_side_fill(const R*, const Dom<R>*, const WallLine*, int, R*, i
 template <typename R>
 hipError_t launch_step2(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int, hipStream_t);
 template <typename R>
-hipError_t launch_diag(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, double*, hipStream_t);
+hipError_t launch_diag(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, R*, int, double*,
+                       hipStream_t);
+template <typename R>
+hipError_t launch_fourier(int, int, const R*, const Dom<R>*, int, int, const Tile*, int, int, double*, double*,
+                          hipStream_t);
 template <typename R>
 hipError_t launch_init(int, int, R*, const Dom<R>*, int, const double*, const double*, const double*, const double*,
                        const double*, hipStream_t);
@@ -770,10 +774,12 @@ int lbm13_batch_diagnostics(lbm13_batch* b, double* out) {
     hipError_t e;
     if (b->precision == LBM13_FP64)
         e = lbm13::launch_diag<double>(b->tile_x, b->tile_y, buf<double>(b, b->cur), doms_dev<double>(b), b->count, all,
-                                       (int)b->all.size(), part, dout, b->stream);
+                                       (int)b->all.size(), part, reinterpret_cast<double*>(b->ws + b->L.wall),
+                                       b->cur, dout, b->stream);
     else
         e = lbm13::launch_diag<float>(b->tile_x, b->tile_y, buf<float>(b, b->cur), doms_dev<float>(b), b->count, all,
-                                      (int)b->all.size(), part, dout, b->stream);
+                                      (int)b->all.size(), part, reinterpret_cast<float*>(b->ws + b->L.wall), b->cur,
+                                      dout, b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "diagnostics launch");
     e = hipMemcpyAsync(out, dout, sizeof(double) * lbm13::kDiagOut * b->count, hipMemcpyDeviceToHost, b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "diagnostics copy");
@@ -782,6 +788,29 @@ int lbm13_batch_diagnostics(lbm13_batch* b, double* out) {
     for (int d = 0; d < b->count; ++d)
         if (out[lbm13::kDiagOut * d + 9] > 0 || !(out[lbm13::kDiagOut * d + 10] > 0))
             return fail(b, LBM13_ENONFINITE, "non-finite population or rho <= 0 in domain " + std::to_string(d));
+    return LBM13_OK;
+}
+
+int lbm13_batch_fourier(lbm13_batch* b, int i, int kx, int ky, double* out) {
+    if (!check_index(b, i) || !out) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    if (!b->has_state[i]) return fail(b, LBM13_ESTATE, "no state");
+    if (!b->has_params[i]) return fail(b, LBM13_ESTATE, "no parameters");
+    const Tile* all = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_all);
+    double* part = reinterpret_cast<double*>(b->ws + b->L.part);
+    double* dout = reinterpret_cast<double*>(b->ws + b->L.diag);  // first 8 values, transient
+    const int ntiles = ((b->nx[i] + b->tile_x - 1) / b->tile_x) * ((b->ny[i] + b->tile_y - 1) / b->tile_y);
+    hipError_t e;
+    if (b->precision == LBM13_FP64)
+        e = lbm13::launch_fourier<double>(b->tile_x, b->tile_y, buf<double>(b, b->cur), doms_dev<double>(b), i, ntiles,
+                                          all, kx, ky, part, dout, b->stream);
+    else
+        e = lbm13::launch_fourier<float>(b->tile_x, b->tile_y, buf<float>(b, b->cur), doms_dev<float>(b), i, ntiles,
+                                         all, kx, ky, part, dout, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "fourier launch");
+    e = hipMemcpyAsync(out, dout, sizeof(double) * 8, hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "fourier copy");
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "fourier sync");
     return LBM13_OK;
 }
 
@@ -974,6 +1003,10 @@ int lbm13_moments(lbm13_ctx* c, double* rho, double* ux, double* uy, double* T) 
 }
 
 int lbm13_diagnostics(lbm13_ctx* c, double out[16]) { return c ? lbm13_batch_diagnostics(c->b, out) : LBM13_EINVAL; }
+
+int lbm13_fourier(lbm13_ctx* c, int kx, int ky, double out[8]) {
+    return c ? lbm13_batch_fourier(c->b, 0, kx, ky, out) : LBM13_EINVAL;
+}
 
 int lbm13_get_state(lbm13_ctx* c, double* dst) { return c ? lbm13_batch_get_state(c->b, 0, dst) : LBM13_EINVAL; }
 

@@ -999,7 +999,161 @@ __global__ __launch_bounds__(256) void diag_final_kernel(const Dom<R>* __restric
     o[8] = umax > 0.0 ? red[6][0] / umax : 0.0;
     o[9] = red[7][0];
     o[10] = red[8][0];
-    for (int j = 11; j < kDiagOut; ++j) o[j] = 0.0;
+    for (int j = 11; j < kDiagOut; ++j) o[j] = 0.0;  // 11..14: wall_flux_kernel
+}
+
+// Energy and mass exchanged with the walls in the next step (sec. 7 walls): an
+// incoming link (x, i) whose source x - v_i lies beyond wall w brings its
+// bounce-back or anti-bounce-back value f_i(x, t+1); an outgoing link (x, j)
+// whose target x + v_j lies beyond w takes f*_j(x, t); a link beyond an x
+// wall and a y wall counts for the x wall.  Incoming and outgoing links pair
+// up with equal |v|, so rest populations cancel and deviations suffice.  One
+// block per domain over the nodes within two nodes of a wall; fixed-shape
+// reduction.  Writes Nu at the West and East walls (energy less B times mass,
+// per unit wall length, over kappa_E dT / nx), the total energy and the total
+// mass taken in.
+template <typename R>
+__device__ __forceinline__ int beyond_wall(const Dom<R>& D, int X, int Y) {
+    if (!D.xper && X < 0) return 0;
+    if (!D.xper && X >= D.nx) return 1;
+    if (!D.yper && Y < 0) return 2;
+    if (!D.yper && Y >= D.ny) return 3;
+    return -1;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void wall_flux_kernel(const R* __restrict__ src, const Dom<R>* __restrict__ doms,
+                                                        R* __restrict__ side, int buf, double* __restrict__ out) {
+    const int d = blockIdx.x;
+    const Dom<R>& D = doms[d];
+    const R* __restrict__ a = src + D.off;
+    const GlobalSrc<R> G{a, D.plane, D.pitch, D.nx, D.ny, D.xper, D.yper};
+    const GlobalSide<R> GS{side, buf};
+    // columns within two nodes of an x wall (every row), then the rows within
+    // two nodes of a y wall outside those columns
+    const int ncx = D.xper ? 0 : min(D.nx, 4), nry = D.yper ? 0 : min(D.ny, 4);
+    const int xlo = D.xper ? 0 : min(2, D.nx), xhi = D.xper ? D.nx : max(D.nx - 2, xlo);
+    const int n1 = ncx * D.ny, n2 = nry * (xhi - xlo);
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // energy W E S N, mass W E S N
+    for (int k = threadIdx.x; k < n1 + n2; k += 256) {
+        int X, Y;
+        if (k < n1) {
+            const int cx = k % ncx;
+            X = (D.nx >= 4 && cx >= 2) ? D.nx - 4 + cx : cx;
+            Y = k / ncx;
+        } else {
+            const int kk = k - n1, ry = kk % nry;
+            X = xlo + kk / nry;
+            Y = (D.ny >= 4 && ry >= 2) ? D.ny - 4 + ry : ry;
+        }
+        R g[13];
+        gather_wall(G, GS, D, X, Y, g);
+        const int c = Y * D.pitch + X;
+#pragma unroll
+        for (int i = 0; i < 13; ++i) {
+            const int wi = beyond_wall(D, X - kVX[i], Y - kVY[i]);
+            if (wi >= 0) {
+                acc[wi] += double(kM[1][i]) * double(g[i]);
+                acc[4 + wi] += double(g[i]);
+            }
+            const int wo = beyond_wall(D, X + kVX[i], Y + kVY[i]);
+            if (wo >= 0) {
+                const double v = double(a[i * D.plane + c]);
+                acc[wo] -= double(kM[1][i]) * v;
+                acc[4 + wo] -= v;
+            }
+        }
+    }
+    __shared__ double red[8][256];
+    const int k = threadIdx.x;
+    for (int j = 0; j < 8; ++j) red[j][k] = acc[j];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (k < h)
+            for (int j = 0; j < 8; ++j) red[j][k] += red[j][k + h];
+        __syncthreads();
+    }
+    if (k != 0) return;
+    double* o = out + d * kDiagOut;
+    const double scale = D.xper ? 0.0 : D.nu_scale / double(D.ny);
+    o[11] = (red[0][0] - D.B * red[4][0]) * scale;
+    o[12] = -(red[1][0] - D.B * red[5][0]) * scale;
+    o[13] = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    o[14] = red[4][0] + red[5][0] + red[6][0] + red[7][0];
+}
+
+// Fourier projection of rho, u_x, u_y and E of one domain (sec. 6 aggregates):
+// sum_{x,y} q exp(-2 pi i (kx x/nx + ky y/ny)), FP64 accumulation.  Pass 1: one
+// block per tile of the domain (its range of the all-tiles table) writes eight
+// partial sums; pass 2: one block combines them in a fixed order.
+template <typename R>
+__global__ __launch_bounds__(256) void fourier_partial_kernel(const R* __restrict__ src,
+                                                              const Dom<R>* __restrict__ doms, int d,
+                                                              const Tile* __restrict__ tiles, int tile_x,
+                                                              int tile_y, int kx, int ky, double* __restrict__ part) {
+    const Dom<R>& D = doms[d];
+    const Tile tl = tiles[D.tile0 + blockIdx.x];
+    const R* __restrict__ a = src + D.off;
+    const long long per = (long long)D.nx * D.ny;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r = threadIdx.x; r < tile_x * tile_y; r += 256) {
+        const int x = tl.x0 + r % tile_x, y = tl.y0 + r / tile_x;
+        if (x >= D.nx || y >= D.ny) continue;
+        const int c = y * D.pitch + x;
+        double rp = 0, e = 0, jx = 0, jy = 0;
+#pragma unroll
+        for (int i = 0; i < 13; ++i) {
+            const double v = double(a[i * D.plane + c]);
+            rp += v;
+            e += double(kM[1][i]) * v;
+            jx += double(kVX[i]) * v;
+            jy += double(kVY[i]) * v;
+        }
+        const double Fx = D.F0x_d + D.gx_d * rp, Fy = D.F0y_d + D.gy_d * rp;
+        const double rho = 1.0 + rp;
+        const double q[4] = {rho, (jx - 0.5 * Fx) / rho, (jy - 0.5 * Fy) / rho, D.E0 + e - D.QE_d};
+        // phase 2 pi m / (nx ny) with m = (kx x ny + ky y nx) mod (nx ny), exact in integers
+        long long m = ((long long)kx * x * D.ny + (long long)ky * y * D.nx) % per;
+        if (m < 0) m += per;
+        double sn, cs;
+        sincospi(2.0 * double(m) / double(per), &sn, &cs);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[2 * j] += q[j] * cs;
+            acc[2 * j + 1] -= q[j] * sn;
+        }
+    }
+    __shared__ double red[8][256];
+    const int k = threadIdx.x;
+    for (int j = 0; j < 8; ++j) red[j][k] = acc[j];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (k < h)
+            for (int j = 0; j < 8; ++j) red[j][k] += red[j][k + h];
+        __syncthreads();
+    }
+    if (k == 0)
+        for (int j = 0; j < 8; ++j) part[blockIdx.x * kDiagPartials + j] = red[j][0];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void fourier_final_kernel(const Dom<R>* __restrict__ doms, int d,
+                                                            const double* __restrict__ part,
+                                                            double* __restrict__ out) {
+    const int n = doms[d].ntiles, k = threadIdx.x;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = k; t < n; t += 256)
+        for (int j = 0; j < 8; ++j) acc[j] += part[t * kDiagPartials + j];
+    __shared__ double red[8][256];
+    for (int j = 0; j < 8; ++j) red[j][k] = acc[j];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (k < h)
+            for (int j = 0; j < 8; ++j) red[j][k] += red[j][k + h];
+        __syncthreads();
+    }
+    if (k == 0)
+        for (int j = 0; j < 8; ++j) out[j] = red[j][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,7 +1183,7 @@ hipError_t launch_step(int tile_x, int tile_y, const R* src, R* dst, const Dom<R
 
 template <typename R>
 hipError_t launch_diag(int tile_x, int tile_y, const R* src, const Dom<R>* doms, int ndom, const Tile* all,
-                       int nall, double* part, double* out, hipStream_t s) {
+                       int nall, double* part, R* side, int buf, double* out, hipStream_t s) {
     if (nall > 0) {
         if (tile_x == 64) {
             const dim3 blk(64, 4);
@@ -1043,6 +1197,18 @@ hipError_t launch_diag(int tile_x, int tile_y, const R* src, const Dom<R>* doms,
         }
     }
     diag_final_kernel<R><<<ndom, 256, 0, s>>>(doms, part, out);
+    wall_flux_kernel<R><<<ndom, 256, 0, s>>>(src, doms, side, buf, out);
+    return hipGetLastError();
+}
+
+// Fourier projection of domain d (ntiles = its tile count in the all-tiles
+// table); out: 8 doubles in device memory.
+template <typename R>
+hipError_t launch_fourier(int tile_x, int tile_y, const R* src, const Dom<R>* doms, int d, int ntiles,
+                          const Tile* all, int kx, int ky, double* part, double* out, hipStream_t s) {
+    if (ntiles > 0)
+        fourier_partial_kernel<R><<<ntiles, 256, 0, s>>>(src, doms, d, all, tile_x, tile_y, kx, ky, part);
+    fourier_final_kernel<R><<<1, 256, 0, s>>>(doms, d, part, out);
     return hipGetLastError();
 }
 
@@ -1117,8 +1283,10 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
                                         hipStream_t);                                                             \
     template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, int,          \
                                             hipStream_t);                                                         \
-    template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*,         \
-                                       double*, hipStream_t);                                                     \
+    template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, R*,     \
+                                       int, double*, hipStream_t);                                                \
+    template hipError_t launch_fourier<R>(int, int, const R*, const Dom<R>*, int, int, const Tile*, int, int,    \
+                                          double*, double*, hipStream_t);                                         \
     template hipError_t launch_init<R>(int, int, R*, const Dom<R>*, int, const double*, const double*,           \
                                        const double*, const double*, const double*, hipStream_t);                 \
     template hipError_t launch_moments<R>(int, int, const R*, const Dom<R>*, int, double*, double*, double*,     \

@@ -25,7 +25,8 @@ FP64, FP32_DEV = 0, 1
 PERIODIC, WALL_ADIABATIC, WALL_DIRICHLET_T = 0, 1, 2
 WEST, EAST, SOUTH, NORTH = 0, 1, 2, 3
 DIAG_NAMES = ("sum_rho", "sum_jx", "sum_jy", "sum_E", "heat_flux", "Nu_mean", "u_max", "asym_abs",
-              "asym_rel", "nonfinite", "rho_min")
+              "asym_rel", "nonfinite", "rho_min", "Nu_west", "Nu_east", "wall_energy_in", "wall_mass_in")
+FOURIER_FIELDS = ("rho", "ux", "uy", "E")
 TILE_SHAPES = ((64, 4), (64, 8), (64, 16), (32, 8), (32, 16))
 _FUSED = ((64, 16), (64, 12), (64, 8), (64, 4), (32, 32), (32, 16), (32, 8), (32, 4))
 FUSED_TILE_SHAPES = {FP32_DEV: _FUSED, FP64: _FUSED}
@@ -86,6 +87,7 @@ def lib():
         "lbm13_step": (i32, [vp, i64]),
         "lbm13_moments": (i32, [vp, dp, dp, dp, dp]),
         "lbm13_diagnostics": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "lbm13_fourier": (i32, [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]),
         "lbm13_get_state": (i32, [vp, dp]),
         "lbm13_set_state": (i32, [vp, dp]),
         "lbm13_steps_done": (i64, [vp]),
@@ -108,6 +110,7 @@ def lib():
         "lbm13_batch_step": (i32, [vp, i64]),
         "lbm13_batch_moments": (i32, [vp, i32, dp, dp, dp, dp]),
         "lbm13_batch_diagnostics": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "lbm13_batch_fourier": (i32, [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_double)]),
         "lbm13_batch_get_state": (i32, [vp, i32, dp]),
         "lbm13_batch_set_state": (i32, [vp, i32, dp]),
         "lbm13_batch_state_bytes": (sz, [vp, i32]),
@@ -254,6 +257,12 @@ class Lattice(_Base):
             self._check(st)
         return dict(zip(DIAG_NAMES, list(out)[:len(DIAG_NAMES)]))
 
+    def fourier(self, kx: int, ky: int) -> dict:
+        """sum q exp(-2 pi i (kx x/nx + ky y/ny)) for q in FOURIER_FIELDS (complex)."""
+        out = (ctypes.c_double * 8)()
+        self._check(lib().lbm13_fourier(self._h, int(kx), int(ky), out))
+        return {q: complex(out[2 * k], out[2 * k + 1]) for k, q in enumerate(FOURIER_FIELDS)}
+
     def get_state(self):
         torch = _torch()
         out = torch.empty((13, self.ny, self.nx), dtype=torch.float64, device="cuda")
@@ -367,6 +376,11 @@ class Batch(_Base):
             self._check(st)
         vals = np.array(list(out)).reshape(self.count, 16)
         return [dict(zip(DIAG_NAMES, row[:len(DIAG_NAMES)])) for row in vals]
+
+    def fourier(self, i: int, kx: int, ky: int) -> dict:
+        out = (ctypes.c_double * 8)()
+        self._check(lib().lbm13_batch_fourier(self._h, int(i), int(kx), int(ky), out))
+        return {q: complex(out[2 * k], out[2 * k + 1]) for k, q in enumerate(FOURIER_FIELDS)}
 
     def get_state(self, i: int):
         torch = _torch()

@@ -12,6 +12,8 @@ its own code.  Recipes:
 * ``thermal_mode``       -- T = T0 + dT cos(kx), rho = 1 - (T - T0)/28, at rest: the
                             non-acoustic diffusive state of sec. 4 (eigenvector
                             (1, 0, -28) of the first-order system, sec. 6).
+* ``transverse_wave``    -- v_y = V0 cos(kx), rho = 1 + (13/56) v_y^2, T uniform: the sec. 6
+                            transverse wave with the initial pressure made uniform.
 * ``cavity_fields``      -- heated cavity at rest, T = T0 + 1e-3 dT U[-1, 1) noise with
                             rho = 1 - (T - T0)/28 (numpy default_rng(seed)), sec. 10.
 * ``cavity_batch``       -- square cavities, side ~ U{64..512}, Ra log-uniform in
@@ -49,6 +51,15 @@ def thermal_mode(nx: int, ny: int, T0: float = -2.0, dT: float = 1e-4, K: int = 
     x, _ = _grid(nx, ny)
     dE = dT * np.cos(2.0 * np.pi * K * x / nx)
     return (1.0 - dE / 28.0, np.zeros((ny, nx)), np.zeros((ny, nx)), T0 + dE)
+
+
+def transverse_wave(nx: int, ny: int, V0: float = 0.02, T0: float = -2.0, a: float = 13.0 / 56.0):
+    """Sec. 6 initial state: v_y = V0 cos(k x), rho = 1 + a v_y^2, uniform T.
+    a = 13/56 makes the initial pressure (14/13) rho + E/26 - u_y^2/2 uniform
+    (first-order system of sec. 6 and XX^eq = -rho u_y^2), so no 2k sound."""
+    x, _ = _grid(nx, ny)
+    uy = V0 * np.cos(2.0 * np.pi * x / nx)
+    return (1.0 + a * uy * uy, np.zeros((ny, nx)), uy, np.full((ny, nx), T0))
 
 
 def cavity_fields(n: int, T0: float = -2.0, dT: float = 0.01, seed: int = 0, ny: int | None = None):

@@ -227,6 +227,51 @@ def test_diagnostics_match_oracle(precision):
     assert gd["asym_abs"] == pytest.approx(od["asym_abs"], rel=1e-8 if precision == 0 else 1e-2, abs=1e-10)
     assert gd["rho_min"] == pytest.approx(od["rho_min"], rel=1e-12 if precision == 0 else 1e-6)
     assert gd["nonfinite"] == 0
+    # energy and mass exchanged with the walls in the next step, wall Nusselt numbers
+    for k in ("Nu_west", "Nu_east", "wall_energy_in", "wall_mass_in"):
+        if precision == 0:
+            assert gd[k] == pytest.approx(od[k], rel=1e-8, abs=1e-12), k
+        else:
+            assert gd[k] == pytest.approx(od[k], rel=5e-2, abs=2e-5), k
+    assert abs(od["wall_energy_in"]) > 1e-6
+
+
+def test_wall_exchange_closes_budgets_on_gpu():
+    """sum E and sum rho change by exactly what the diagnostics report the walls
+    exchange (plus the volumic energy source)."""
+    lbm13 = _lb()
+    say("wall energy / mass budget on GPU")
+    nx, ny, Q = 40, 30, 2e-6
+    lat = lbm13.Lattice(nx, ny, lbm13.FP64)
+    lat.set_params(sides=lbm13.make_sides((2, 2, 1, 1), (0.01, 0.0, 0.02, -0.01), (-1.99, -2.01, 0, 0)),
+                   g=(0.0, -1e-4), Q_E=Q)
+    lat.init_moments(*workloads.cavity_fields(nx, ny=ny, seed=5, dT=0.02))
+    lat.step(9)
+    for _ in range(3):
+        d0 = lat.diagnostics()
+        lat.step(1)
+        d1 = lat.diagnostics()
+        assert abs(d1["sum_E"] - d0["sum_E"] - d0["wall_energy_in"] - Q * nx * ny) < 1e-11 * abs(d0["sum_E"])
+        assert abs(d1["sum_rho"] - d0["sum_rho"] - d0["wall_mass_in"]) < 1e-12 * d0["sum_rho"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fourier_projection_matches_oracle(precision):
+    lbm13 = _lb()
+    say("fourier projections precision %d" % precision)
+    nx, ny = 96, 40
+    fields = workloads.transverse_wave(nx, ny, 0.03)
+    fields = (fields[0] + 1e-3 * np.cos(2 * np.pi * 3 * np.arange(ny) / ny)[:, None], fields[1] + 0.01,
+              fields[2], fields[3])
+    lat, gs, gm, fs, om, f, po, so = run_both(nx, ny, fields, 25, (0, 0, 2, 1), (0, 0, 0.02, 0),
+                                              (0, 0, -1.99, 0), precision=precision)
+    N = nx * ny
+    tol = 1e-10 if precision == 0 else 1e-5
+    for kx, ky in ((0, 0), (1, 0), (2, 0), (0, 3), (-7, 5), (97, -41)):
+        g, o = lat.fourier(kx, ky), oracle.fourier(f, po, kx, ky)
+        for q in lbm13.FOURIER_FIELDS:
+            assert abs(g[q] - o[q]) <= tol * N * (3.0 if q == "E" else 1.0), (kx, ky, q, g[q], o[q])
+    lat.destroy()
 
 
 def test_conduction_nusselt_is_one_on_gpu():
@@ -237,7 +282,10 @@ def test_conduction_nusselt_is_one_on_gpu():
     d = lat.set_params(sides=lbm13.make_sides((2, 2, 0, 0), (0, 0, 0, 0), (-2 + dT / 2, -2 - dT / 2, 0, 0)))
     lat.init_moments(*workloads.rest_fields(W, ny))
     lat.step(int(8 * W * W / d["kappa"]))
-    assert lat.diagnostics()["Nu_mean"] == pytest.approx(1.0, abs=2e-3)
+    dg = lat.diagnostics()
+    assert dg["Nu_mean"] == pytest.approx(1.0, abs=2e-3)
+    assert dg["Nu_west"] == pytest.approx(1.0, abs=2e-3)
+    assert dg["Nu_east"] == pytest.approx(1.0, abs=2e-3)
 
 
 # --------------------------------------------------------------------------- batched form
@@ -272,6 +320,10 @@ def test_batch_matches_oracle_per_domain():
                 assert_fp64(b.get_state(i).cpu().numpy(), gm, oracle.collide(f, po), om)
             else:
                 assert_fp32(gm, om)
+            for kx, ky in ((1, 0), (0, 2)):
+                g, o = b.fourier(i, kx, ky), oracle.fourier(f, po, kx, ky)
+                for q in lbm13.FOURIER_FIELDS:
+                    assert abs(g[q] - o[q]) <= (1e-10 if precision == 0 else 3e-5) * nx * ny, (i, q)
 
 
 # --------------------------------------------------------------------------- runtime
@@ -547,6 +599,32 @@ def test_every_two_step_tile_shape(precision):
             else:
                 assert_fp32(gm, om)
             lat.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_transverse_wave_energy_growth_matches_oracle(precision):
+    """Sec. 6 transverse wave (v_y = V cos kx) for one period of the 2k sound
+    wave: moments and the growth of E~ = sum E cos 2kx against the oracle."""
+    lbm13 = _lb()
+    nx, ny, V0 = 256, 4, 0.02
+    po = oracle.params()
+    period = int(round(nx / (2 * np.sqrt(oracle.derive(po)[1]["cs2"]))))
+    say("transverse wave %dx%d precision %d, %d steps" % (nx, ny, precision, period + 10))
+    lat, gs, gm, fs, om, f, po, so = run_both(nx, ny, workloads.transverse_wave(nx, ny, V0), period + 10,
+                                              precision=precision, spl=2)
+    if precision == 0:
+        assert_fp64(gs, gm, fs, om)
+    else:
+        assert_fp32(gm, om)
+    k = 2 * np.pi / nx
+    c2k = np.cos(2 * k * np.arange(nx))[None, :]
+    # E from the read-back T and u (T = E - 13/2 |u|^2)
+    e_gpu = ((gm[3] + 6.5 * (gm[1] ** 2 + gm[2] ** 2)) * c2k).sum()
+    e_ora = ((om[3] + 6.5 * (om[1] ** 2 + om[2] ** 2)) * c2k).sum()
+    e0 = (workloads.transverse_wave(nx, ny, V0)[3] + 6.5 * workloads.transverse_wave(nx, ny, V0)[2] ** 2)
+    e0 = (e0 * c2k).sum()
+    assert abs((e_gpu - e0) - (e_ora - e0)) <= (1e-9 if precision == 0 else 2e-3) * abs(e_ora - e0)
+    lat.destroy()
 
 
 @pytest.mark.parametrize("precision", [0, 1])

@@ -346,6 +346,44 @@ def test_thermal_wave_decays_without_sound():
     assert len(set(signs)) == 2
 
 
+def transverse_energy_growth(p, nx, V0, ny=2, t0=10):
+    """Sec. 6 aggregate E~ = sum E cos 2kx: its change over one period of the 2k
+    sound wave (so residual sound averages out), after t0 start-up steps."""
+    st, d = oracle.derive(p)
+    k = 2 * np.pi / nx
+    period = int(round(nx / (2 * np.sqrt(d["cs2"]))))
+    M = oracle.matrix()[0]
+    x = np.arange(nx)[None, :]
+
+    def e_tilde(f):
+        return float((np.einsum("i,iyx->yx", M[1], f) * np.cos(2 * k * x)).sum())
+
+    f = oracle.run(oracle.init(*workloads.transverse_wave(nx, ny, V0), p), p, oracle.sides(), t0)
+    e0 = e_tilde(f)
+    e1 = e_tilde(oracle.run(f, p, oracle.sides(), period))
+    return e1 - e0, d, k, period
+
+
+@pytest.mark.parametrize("nx", [256, 512])
+def test_transverse_wave_energy_grows_as_nu_k2_V2(nx):
+    """Sec. 6: a transverse wave v_y = V cos kx (initial density balancing the
+    pressure, so no 2k sound) makes E~ = sum E cos 2kx grow in proportion to
+    nu k^2 V^2 at fixed Pr.  The growth is the diffusion of the internal energy
+    E - 13 u^2, which a uniform T = E - 13/2 u^2 leaves varying as -13/2 V^2
+    cos^2 kx: its 2k part (amplitude 13/4 V^2 over N/2 nodes) relaxes at
+    kappa (2k)^2, so E~ grows by 13/4 V^2 N/2 (e^(-lambda t0) - e^(-lambda t1)),
+    initially 13/2 kappa k^2 V^2 N with kappa = nu / Pr."""
+    ny = 2
+    for s_XX in (1.2, 1.5, 1.85):
+        p = oracle.params(s_XX=s_XX)
+        g1, d, k, period = transverse_energy_growth(p, nx, 0.02, ny)
+        g2, *_ = transverse_energy_growth(p, nx, 0.01, ny)
+        assert g1 / g2 == pytest.approx(4.0, rel=2e-3)  # quadratic in V
+        lam = d["kappa"] * 4 * k * k
+        model = 3.25 * 0.02 ** 2 * nx * ny / 2 * (np.exp(-lam * 10) - np.exp(-lam * (10 + period)))
+        assert g1 == pytest.approx(model, rel=0.03), (s_XX, g1 / model)
+
+
 # --------------------------------------------------------------------------- secs. 5, 7, 8 flows
 
 def test_buoyancy_initial_growth_is_linear():
@@ -409,7 +447,11 @@ def test_conduction_is_linear_and_nusselt_is_one():
     (rho, ux, uy, T), f = _channel(p, s, W, int(8 * W * W / d["kappa"]), ny=3)
     xi = np.arange(W) + 0.5
     np.testing.assert_allclose(T[0], p.E0 + dT / 2 - dT * xi / W, atol=2e-3 * dT)
-    assert oracle.diagnostics(f, p, s)["Nu_mean"] == pytest.approx(1.0, abs=2e-3)
+    dg = oracle.diagnostics(f, p, s)
+    assert dg["Nu_mean"] == pytest.approx(1.0, abs=2e-3)
+    # the energy crossing each temperature wall per step is the conduction flux
+    assert dg["Nu_west"] == pytest.approx(1.0, abs=2e-3)
+    assert dg["Nu_east"] == pytest.approx(1.0, abs=2e-3)
 
 
 def test_derive_rejects_unstable_rates():
@@ -511,6 +553,51 @@ def test_energy_source_budget():
     N = 16 * 16
     assert abs(d1["sum_E"] - d0["sum_E"] - t * N * Q) < 1e-11 * N
     assert abs(d1["sum_rho"] - d0["sum_rho"]) < 1e-12 * N
+
+
+@pytest.mark.parametrize("sides", [
+    ((2, 2, 1, 1), (0.01, 0.0, 0.02, -0.01), (-1.99, -2.01, 0, 0)),
+    ((1, 1, 2, 2), (0.0, -0.02, 0.0, 0.01), (0, 0, -1.98, -2.0)),
+    ((0, 0, 2, 1), (0, 0, 0.03, 0.0), (0, 0, -2.01, 0))])
+def test_wall_energy_exchange_closes_the_energy_budget(sides):
+    """The energy the walls exchange in a step (incoming minus outgoing link
+    populations weighted by the E row of M) plus the volumic source is exactly
+    the change of sum E, and the mass they exchange (anti-bounce-back links
+    are not mass-tight) the change of sum rho: streaming and collision conserve
+    both elsewhere."""
+    Q = 2e-6
+    p = oracle.params(Q_E=Q, gx=0.0, gy=-1e-4)
+    s = oracle.sides(*sides)
+    nx, ny = 30, 20
+    f = oracle.init(*workloads.cavity_fields(nx, ny=ny, seed=7, dT=0.02), p)
+    f = oracle.run(f, p, s, 7)
+    for _ in range(4):
+        d0 = oracle.diagnostics(f, p, s)
+        f = oracle.step(f, p, s)
+        d1 = oracle.diagnostics(f, p, s)
+        assert abs(d1["sum_E"] - d0["sum_E"] - d0["wall_energy_in"] - Q * nx * ny) < 1e-11 * abs(d0["sum_E"])
+        assert abs(d1["sum_rho"] - d0["sum_rho"] - d0["wall_mass_in"]) < 1e-12 * d0["sum_rho"]
+        assert abs(d0["wall_energy_in"]) > 1e-6
+
+
+def test_fourier_projections_of_known_fields():
+    """sum q exp(-2 pi i (kx x/nx + ky y/ny)) of initial fields in closed form:
+    rho = 1 + a cos(kx), ux = b cos(kx): a N/2 and b N/2; E = T0 + 13/2 ux^2 has
+    no k component and 13/2 b^2 N/4 at 2k; ux = c sin(2 pi y/ny) gives -i c N/2
+    at ky = 1."""
+    p = oracle.params()
+    n, a, b = 32, 0.05, 0.02
+    N = n * n
+    f = oracle.init(*workloads.periodic_wave(n, a_rho=a, a_u=b), p)
+    q1, q2 = oracle.fourier(f, p, 1, 0), oracle.fourier(f, p, 2, 0)
+    assert q1["rho"] == pytest.approx(a * N / 2, abs=1e-11)
+    assert q1["ux"] == pytest.approx(b * N / 2, abs=1e-11)
+    assert abs(q1["uy"]) < 1e-13 and abs(q1["E"]) < 1e-10
+    assert q2["E"] == pytest.approx(6.5 * b * b * N / 4, abs=1e-10)
+    assert oracle.fourier(f, p, 0, 0)["rho"] == pytest.approx(N, abs=1e-10)
+    g = oracle.init(*workloads.shear_acoustic(48, 40, a_u=0.01), p)
+    qy = oracle.fourier(g, p, 0, 1)
+    assert qy["ux"] == pytest.approx(-0.01j * 48 * 40 / 2, abs=1e-11)
 
 
 def test_adiabatic_wall_with_energy_source_gives_semi_parabola():
