@@ -628,6 +628,55 @@ def test_transverse_wave_energy_growth_matches_oracle(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_wave_rates_match_linear_theory(precision):
+    """4096^2 shear + acoustic wave in the benchmark's launch configuration, 20000
+    steps: the shear mode decays at the eigenvalue of the linear amplification
+    matrix (nu k^2 = 1.4707e-7 per step), the sound wave oscillates at its
+    eigenfrequency and is damped at its rate, and the initial density wave at
+    uniform T splits into sound (28/(28 + B) of it) and the diffusive mode."""
+    lbm13 = _lb()
+    import bench
+    from scipy.optimize import curve_fit
+    from oracle import linear
+    n = 4096
+    k = 2 * np.pi / n
+    po = oracle.params()
+    lam_s = [m for m in linear.hydro_modes(po, (0, k)) if abs(m[1]) < 1e-9][0][0]
+    sound = [m for m in linear.hydro_modes(po, (k, 0)) if m[1] > 1e-6][0]
+    B = oracle.derive(po)[1]["B"]
+    cfg = bench.BENCH_CONFIG[precision]
+    say("full-size wave rates precision %d, 20000 steps" % precision)
+    lat = lbm13.Lattice(n, n, precision)
+    lat.set_fused_tile(*cfg["fused_tile"])
+    lat.set_steps_per_launch(cfg["spl"])
+    lat.set_params()
+    lat.init_moments(*workloads.shear_acoustic(n))
+    lat.use_graph(100)
+    ts, shear, rho = [], [], []
+    for t in range(0, 20001, 100):
+        if t:
+            lat.step(100)
+        ts.append(t)
+        shear.append(lat.fourier(0, 1)["ux"])
+        rho.append(lat.fourier(1, 0)["rho"].real)
+    lat.destroy()
+    ts, shear, rho = np.array(ts, float), np.array(shear), np.array(rho)
+    N = n * n
+    assert shear[0] == pytest.approx(-0.01j * N / 2, rel=1e-9)
+    rate = -np.polyfit(ts, np.log(np.abs(shear)), 1)[0]
+    assert rate == pytest.approx(lam_s, rel=2e-3)
+
+    def model(t, A, w, ph, G, C, D):
+        return A * np.cos(w * t + ph) * np.exp(-G * t) + C + D * t
+    a = 1e-3 * N / 2
+    popt, _ = curve_fit(model, ts, rho, p0=(a, sound[1], 0.0, sound[0], a * B / (28 + B), 0.0), maxfev=20000)
+    assert popt[1] == pytest.approx(sound[1], rel=2e-5)
+    assert popt[3] == pytest.approx(sound[0], rel=0.15)
+    assert popt[0] == pytest.approx(a * 28 / (28 + B), rel=2e-3)
+    assert popt[4] == pytest.approx(a * B / (28 + B), rel=2e-2)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_interior_kernel_switch_is_bit_exact(precision):
     """Two-step launches with the interior tiles on their own kernel (run
     concurrently with the general kernel) and with every tile on the general
