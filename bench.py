@@ -46,21 +46,25 @@ def kernel_sha():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(key):
-    """HBM bytes per launch of the timed kernel from the committed rocprofv3
-    counter runs, if they were taken on the current kernel source; else None."""
+def measured_traffic(key, launch):
+    """HBM bytes per launch of the timed form from the committed rocprofv3
+    counter runs, if they were taken on the current kernel source and in the
+    same launch configuration; else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     rec = t.get(key)
-    if not rec or t.get("kernel_source_sha") != kernel_sha():
+    if not rec or t.get("kernel_source_sha") != kernel_sha() or rec.get("launch") != json.loads(json.dumps(launch)):
         return None
     return rec.get("bytes_per_launch")
 
 
-def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k):
+def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0):
+    """Time one form on the n x n wave.  cfg fixes the launch configuration;
+    tune_steps > 0 lets the library's autotuner pick it on this device instead
+    (from a fresh copy of the state) and the choice is returned as `launch`."""
     import torch
 
     from paper_1401_0188_amd import lbm13, workloads
@@ -69,8 +73,15 @@ def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k):
     lat.set_tile(*cfg["tile"])
     lat.set_fused_tile(*cfg["fused_tile"])
     lat.set_steps_per_launch(cfg["spl"])
+    if "interior_kernel" in cfg:
+        lat.set_interior_kernel(cfg["interior_kernel"])
     lat.set_params()
-    lat.init_moments(*workloads.shear_acoustic(n))
+    fields = workloads.shear_acoustic(n)
+    lat.init_moments(*fields)
+    if tune_steps > 0:
+        lat.autotune(tune_steps)
+        lat.init_moments(*fields)
+    launch = lat.launch_config()
     if graph_k:
         lat.use_graph(graph_k)
     lat.step(warmup)
@@ -101,9 +112,10 @@ def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k):
     del lat
     torch.cuda.empty_cache()
     spl = cfg["spl"]
+    spl = launch["steps_per_launch"]
     return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=kern_ms / steps * spl,
                 mlups=nodes * steps / wall / 1e6, kernel_mlups=nodes / (kern_ms / steps * 1e-3) / 1e6,
-                mass_drift=drift, nodes=nodes, spl=spl)
+                mass_drift=drift, nodes=nodes, spl=spl, launch=launch)
 
 
 def cavity_specs(count=64, seed=4):
@@ -362,6 +374,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tune-steps", type=int, default=40,
+                    help="steps per candidate of the launch autotuner for the wave forms (0: fixed configuration)")
+    ap.add_argument("--launch-fp32", type=json.loads, metavar="JSON",
+                    help="fix the FP32 launch configuration (a `launch` object of an earlier run; no autotuning)")
+    ap.add_argument("--launch-fp64", type=json.loads, metavar="JSON",
+                    help="fix the FP64 launch configuration (as --launch-fp32)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -384,11 +402,21 @@ def main():
     n = args.size
     graph_k = 0 if args.no_graph else GRAPH_K
     log("fp32-deviation %dx%d: %d warmup + %d steps" % (n, n, args.warmup, args.steps))
-    r32 = run_form(lbm13.FP32_DEV, n, args.steps, args.warmup, args.diag_every, BENCH_CONFIG[1], graph_k)
-    log("fp32: %.1f MLUPS, kernel %.4f ms per launch" % (r32["mlups"], r32["kernel_ms_per_launch"]))
+    def fixed(launch):
+        return dict(spl=launch["steps_per_launch"], tile=tuple(launch["tile"]), fused_tile=tuple(launch["fused_tile"]),
+                    interior_kernel=bool(launch["interior_kernel"]))
+    cfg32, cfg64 = dict(BENCH_CONFIG[1]), dict(BENCH_CONFIG[0])
+    tune32 = tune64 = args.tune_steps
+    if args.launch_fp32:
+        cfg32, tune32 = fixed(args.launch_fp32), 0
+    if args.launch_fp64:
+        cfg64, tune64 = fixed(args.launch_fp64), 0
+    r32 = run_form(lbm13.FP32_DEV, n, args.steps, args.warmup, args.diag_every, cfg32, graph_k, tune32)
+    log("fp32: %.1f MLUPS, kernel %.4f ms per launch, %s" % (r32["mlups"], r32["kernel_ms_per_launch"],
+                                                           r32["launch"]))
     fp64_steps = args.fp64_steps if args.fp64_steps >= 0 else max(2, args.steps // 2)
     log("fp64 %dx%d: %d steps" % (n, n, fp64_steps))
-    r64 = run_form(lbm13.FP64, n, fp64_steps, max(2, args.warmup // 2), args.diag_every, BENCH_CONFIG[0], graph_k)
+    r64 = run_form(lbm13.FP64, n, fp64_steps, max(2, args.warmup // 2), args.diag_every, cfg64, graph_k, tune64)
     log("fp64: %.1f MLUPS, kernel %.4f ms per launch" % (r64["mlups"], r64["kernel_ms_per_launch"]))
     plain_cfg = dict(BENCH_CONFIG[0], spl=1)
     r64p = run_form(lbm13.FP64, n, fp64_steps, max(2, args.warmup // 2), args.diag_every, plain_cfg, graph_k)
@@ -399,9 +427,12 @@ def main():
         log("cpu baseline (oracle) for about %.0f s" % args.cpu_seconds)
         cpu = cpu_baseline(n, args.cpu_seconds)
 
-    roof32 = roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, measured_traffic("fp32_two_step"), spl=2)
-    roof64 = roofline(r64["nodes"], r64["kernel_ms_per_launch"], 0, measured_traffic("fp64_two_step"), spl=2)
-    roof64p = roofline(r64p["nodes"], r64p["kernel_ms_per_launch"], 0, measured_traffic("fp64"), spl=1)
+    roof32 = roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, measured_traffic("fp32", r32["launch"]),
+                      spl=r32["spl"])
+    roof64 = roofline(r64["nodes"], r64["kernel_ms_per_launch"], 0, measured_traffic("fp64", r64["launch"]),
+                      spl=r64["spl"])
+    roof64p = roofline(r64p["nodes"], r64p["kernel_ms_per_launch"], 0, measured_traffic("fp64_plain", r64p["launch"]),
+                       spl=1)
     out = {
         "metric": METRIC,
         "value": round(r32["mlups"], 1),
@@ -416,13 +447,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "periodic %dx%d transverse shear + acoustic wave" % (n, n), "nx": n, "ny": n,
-                   "form": "fp32-deviation, two steps per launch",
-                   "fused_tile": list(BENCH_CONFIG[1]["fused_tile"]), "graph_steps": graph_k,
-                   "diag_every": args.diag_every},
+                   "form": "fp32-deviation", "launch": r32["launch"],
+                   "launch_choice": "autotuned on this device" if tune32 else "fixed",
+                   "graph_steps": graph_k, "diag_every": args.diag_every},
         "roofline": roof32,
         "cpu_baseline": cpu,
         "fp64": {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
-                 "roofline": roof64, "steps": fp64_steps, "form": "fp64, two steps per launch"},
+                 "roofline": roof64, "steps": fp64_steps, "form": "fp64", "launch": r64["launch"]},
         "fp64_plain": {"value": round(r64p["mlups"], 1), "unit": "MLUPS",
                        "ms_per_step": round(r64p["ms_per_step"], 5), "roofline": roof64p,
                        "form": "fp64, one step per launch"},

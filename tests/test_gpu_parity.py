@@ -193,7 +193,7 @@ def test_fp32_shear_wave_matches_oracle():
 @pytest.mark.parametrize("precision", [0, 1])
 def test_full_size_4096_matches_oracle(precision):
     """The 4096^2 periodic shear + acoustic wave at full size, a few steps, in
-    the tile shape the benchmark uses."""
+    the default launch configuration of the benchmark (whole state)."""
     lbm13 = _lb()
     from bench import BENCH_CONFIG
     cfg = BENCH_CONFIG[precision]
@@ -204,6 +204,51 @@ def test_full_size_4096_matches_oracle(precision):
         assert_fp64(gs, gm, fs, om)
     else:
         assert_fp32(gm, om, tol=1e-6)
+
+
+@pytest.fixture(scope="module")
+def oracle_wave_4096():
+    fields = workloads.shear_acoustic(4096)
+    po = oracle.params()
+    f = oracle.run(oracle.init(*fields, po), po, oracle.sides(), 4)
+    return fields, oracle.moments(f, po)
+
+
+def launch_candidates(lbm13, precision):
+    """Every launch configuration the autotuner chooses from."""
+    out = [dict(spl=1, tile=t) for t in lbm13.TILE_SHAPES]
+    for ft in lbm13.FUSED_TILE_SHAPES[precision]:
+        for on in (True, False):
+            out.append(dict(spl=2, fused_tile=ft, interior_kernel=on))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_4096_every_launch_configuration(precision, oracle_wave_4096):
+    """4 steps of the 4096^2 wave in every configuration the benchmark's
+    autotuner may pick (moments against the oracle)."""
+    lbm13 = _lb()
+    fields, om = oracle_wave_4096
+    for cand in launch_candidates(lbm13, precision):
+        say("full size 4096^2 precision %d, launch %s" % (precision, cand))
+        lat = lbm13.Lattice(4096, 4096, precision)
+        if cand["spl"] == 1:
+            lat.set_tile(*cand["tile"])
+        else:
+            lat.set_fused_tile(*cand["fused_tile"])
+            lat.set_interior_kernel(cand["interior_kernel"])
+        lat.set_steps_per_launch(cand["spl"])
+        lat.set_params()
+        lat.init_moments(*fields)
+        lat.step(4)
+        gm = [t.cpu().numpy() for t in lat.moments()]
+        lat.destroy()
+        if precision == 0:
+            assert np.abs(gm[0] - om[0]).max() <= 1e-12 * np.abs(om[0]).max()
+            assert max(np.abs(gm[1] - om[1]).max(), np.abs(gm[2] - om[2]).max()) <= 1e-12
+            assert np.abs(gm[3] - om[3]).max() <= 1e-12 * np.abs(om[3]).max()
+        else:
+            assert_fp32(gm, om, tol=1e-6)
 
 
 # --------------------------------------------------------------------------- diagnostics
