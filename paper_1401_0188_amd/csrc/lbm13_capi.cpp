@@ -297,15 +297,16 @@ int rebuild(lbm13_batch* b) {
     const long long es = b->precision == LBM13_FP64 ? 8 : 4;
     for (int d = 0; d < b->count; ++d) {
         // interior tiles address the 13 planes with 32-bit byte offsets
-        const bool small = b->split && (13LL * b->L.plane[d] + 2LL * b->L.pitch[d] + 2) * es <= (long long)INT32_MAX;
+        const bool small = (13LL * b->L.plane[d] + 2LL * b->L.pitch[d] + 2) * es <= (long long)INT32_MAX;
         for (int y0 = 0; y0 < b->ny[d]; y0 += b->fth)
             for (int x0 = 0; x0 < b->nx[d]; x0 += b->ftw) {
                 // flag 2: interior tile (region plus its gather reach inside the
-                // domain and at least two nodes from every wall, no wrap)
+                // domain and at least two nodes from every wall, no wrap); with the
+                // interior kernel off it runs the general kernel's fast path
                 const bool in = small && x0 >= 4 && x0 + b->ftw + 4 <= b->nx[d] && y0 >= 4 &&
                                 y0 + b->fth + 4 <= b->ny[d];
-                if (in) b->fused.push_back(Tile{d, x0, y0, 2});
-                else fedge.push_back(Tile{d, x0, y0, 0});
+                if (in && b->split) b->fused.push_back(Tile{d, x0, y0, 2});
+                else fedge.push_back(Tile{d, x0, y0, in ? 2 : 0});
             }
     }
     b->nfint = (int)b->fused.size();

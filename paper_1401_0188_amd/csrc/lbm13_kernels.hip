@@ -561,11 +561,54 @@ __global__ __launch_bounds__(NT) void step2_kernel(const R* __restrict__ src, R*
     const int ox = tl.x0 - 2, oy = tl.y0 - 2;
     const int tid = threadIdx.x;
 
+    if (tl.flags & 2) {
+        // Interior tile (when the interior kernel is not used): gathers through
+        // one buffer descriptor as in step2_interior_kernel, the whole region in
+        // LDS, no wall, wrap or bounds logic.
+        constexpr int es = (int)sizeof(R);
+        const int P = D.pitch, S = D.plane;
+        const __amdgpu_buffer_rsrc_t in = buffer_rsrc(a - (2 * P + 2), (unsigned)((13 * S + 2 * P + 2) * es));
+        R h[NI][13];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int r = min(tid + k * NT, RW * RH - 1);
+            const unsigned c = (unsigned)(((oy + r / RW) * P + ox + r % RW) * es);
+#pragma unroll
+            for (int i = 0; i < 13; ++i)
+                h[k][i] = buffer_load<R>(in, c, (unsigned)((i * S + (2 - kVY[i]) * P + 2 - kVX[i]) * es));
+        }
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int r = tid + k * NT;
+            if (D.collide) collide(h[k], D);
+            if (r < RW * RH) {
+#pragma unroll
+                for (int i = 0; i < 13; ++i) lds[i * RH * RW + r] = h[k][i];
+            }
+        }
+        __syncthreads();
+        const __amdgpu_buffer_rsrc_t out = buffer_rsrc(o, (unsigned)(13 * S * es));
+        for (int r = tid; r < TW * TH; r += NT) {
+            const int lx = r % TW + 2, ly = r / TW + 2;
+            const unsigned c = (unsigned)(((oy + ly) * P + ox + lx) * es);
+            R q[13];
+#pragma unroll
+            for (int i = 0; i < 13; ++i) q[i] = lds[(i * RH + ly - kVY[i]) * RW + lx - kVX[i]];
+            if (D.collide) collide(q, D);
+#pragma unroll
+            for (int i = 0; i < 13; ++i) buffer_store_nt<R>(q[i], out, c, (unsigned)(i * S * es));
+        }
+        return;
+    }
+
     // Phase 1: all gathers of a thread's region nodes are issued before the
     // first collision.  Region nodes beyond a wall (or past the region's end)
     // gather from a clamped in-domain node and store nothing.
     const GlobalSrc<R> G{a, D.plane, D.pitch, D.nx, D.ny, D.xper, D.yper};
     const GlobalSide<R> GS{side, from};
+    const bool region_walls = (!D.xper && (ox < 2 || ox + RW > D.nx - 2)) || (!D.yper && (oy < 2 || oy + RH > D.ny - 2));
+    const bool tile_walls = (!D.xper && (tl.x0 < 2 || tl.x0 + TW > D.nx - 2)) ||
+                            (!D.yper && (tl.y0 < 2 || tl.y0 + TH > D.ny - 2));
     R g[NI][13];
     int Xs[NI], Ys[NI];
     bool valid[NI];
@@ -582,9 +625,9 @@ __global__ __launch_bounds__(NT) void step2_kernel(const R* __restrict__ src, R*
         Xs[k] = X;
         Ys[k] = Y;
         valid[k] = v;
-        const bool xw = !D.xper && (X < 2 || X >= D.nx - 2);
-        const bool yw = !D.yper && (Y < 2 || Y >= D.ny - 2);
-        if (xw || yw) gather_wall(G, GS, D, X, Y, g[k]);
+        // a region that reaches a wall gathers every node with the wall gather
+        // (the bulk result away from the wall), so no wavefront runs both
+        if (region_walls) gather_wall(G, GS, D, X, Y, g[k]);
         else gather_bulk(a, D, X, Y, g[k]);
     }
 #pragma unroll
@@ -628,7 +671,7 @@ __global__ __launch_bounds__(NT) void step2_kernel(const R* __restrict__ src, R*
         if (X >= D.nx || Y >= D.ny) continue;
         R g[13];
         const bool near = (!D.xper && (X < 2 || X >= D.nx - 2)) || (!D.yper && (Y < 2 || Y >= D.ny - 2));
-        if (near) {
+        if (tile_walls) {
             gather_wall(L, LS, D, X, Y, g);
         } else {
 #pragma unroll
