@@ -209,11 +209,16 @@ int lbm13_launch_config(const lbm13_ctx *ctx, int cfg[6]);
  * replays for every full block of k steps; k = 0 switches graphs off. */
 int lbm13_use_graph(lbm13_ctx *ctx, int k);
 
-/* Time steps advanced per kernel launch: 1, or 2 (each workgroup advances its
+/* Time steps advanced per kernel launch: 1, 2 (each workgroup advances its
  * tile and a two-node halo by one step into LDS, then the tile by a second
  * step; same arithmetic per node, so results equal two single steps, with
- * about half the HBM traffic per step).  An odd remainder of lbm13_step(n) is
- * done by a single-step launch.  EINVAL for other values. */
+ * about half the HBM traffic per step) or 3 (tile + 4-node halo, then tile +
+ * 2-node halo, then the tile: a third of the HBM traffic per step; only for
+ * domains periodic on both axes whose sides are multiples of the two-step
+ * tile, which must be a three-step shape: FP32 (64, 16), (32, 32), (64, 8),
+ * (32, 16); FP64 (64, 8), (32, 16), (32, 8); lbm13_step returns EINVAL
+ * otherwise).  A remainder of lbm13_step(n) is done by shorter launches.
+ * EINVAL for other values. */
 int lbm13_set_steps_per_launch(lbm13_ctx *ctx, int k);
 
 /* Tile of the two-steps-per-launch kernels: (64, 16), (64, 12), (64, 8),

@@ -37,6 +37,8 @@ template <typename R>
 hipError_t launch_fourier(int, int, const R*, const Dom<R>*, int, int, const Tile*, int, int, double*, double*,
                           hipStream_t);
 template <typename R>
+hipError_t launch_step3(int, int, const R*, R*, const Dom<R>*, const Tile*, int, hipStream_t);
+template <typename R>
 hipError_t launch_init(int, int, R*, const Dom<R>*, int, const double*, const double*, const double*, const double*,
                        const double*, hipStream_t);
 template <typename R>
@@ -59,6 +61,15 @@ const int kShapes[][2] = {{64, 4}, {64, 8}, {64, 16}, {32, 8}, {32, 16}};
 // fused (two steps per launch) tile shapes, as compiled in the kernels
 const int kFusedShapes[][2] = {{64, 16}, {64, 12}, {64, 8}, {64, 4}, {32, 32}, {32, 16}, {32, 8}, {32, 4}};
 
+// three steps per launch: compiled tile shapes per precision (FP64 first)
+const int kStep3Shapes[2][4][2] = {{{64, 8}, {32, 16}, {32, 8}, {0, 0}}, {{64, 16}, {32, 32}, {64, 8}, {32, 16}}};
+
+bool step3_shape(int precision, int tw, int th) {
+    for (auto& f : kStep3Shapes[precision == LBM13_FP64 ? 0 : 1])
+        if (f[0] == tw && f[1] == th) return true;
+    return false;
+}
+
 // whether the region of a two-step tile fits the LDS of one workgroup
 bool fused_fits(int precision, int tw, int th) {
     const int es = precision == LBM13_FP64 ? 8 : 4;
@@ -74,7 +85,7 @@ bool valid_shape(int tx, int ty) {
 }
 
 struct Layout {
-    size_t doms, coef, tiles_all, tiles_run, tiles_fused, part, diag, lines, wall, bufA, bufB, total;
+    size_t doms, coef, tiles_all, tiles_run, tiles_fused, tiles_fused3, part, diag, lines, wall, bufA, bufB, total;
     size_t buf_bytes;
     int tmax, tfmax;
     long long nlines_max;
@@ -123,6 +134,7 @@ bool make_layout(int count, const int* nx, const int* ny, int precision, Layout&
     L.tiles_all = p; p = align_up(p + sizeof(Tile) * tmax, kAlign);
     L.tiles_run = p; p = align_up(p + sizeof(Tile) * tmax, kAlign);
     L.tiles_fused = p; p = align_up(p + sizeof(Tile) * tfmax, kAlign);
+    L.tiles_fused3 = p; p = align_up(p + sizeof(Tile) * tfmax, kAlign);
     L.part = p;      p = align_up(p + sizeof(double) * lbm13::kDiagPartials * tmax, kAlign);
     L.diag = p;      p = align_up(p + sizeof(double) * lbm13::kDiagOut * count, kAlign);
     L.nlines_max = lines;
@@ -194,9 +206,10 @@ struct lbm13_batch {
     std::vector<double> coef_host;
     std::vector<int> sides_kind;          // 4 per domain
     std::vector<char> has_params, has_state;
-    std::vector<Tile> all, run, fused;
+    std::vector<Tile> all, run, fused, fused3;
+    bool step3_ok = false;                // three-step launches possible (see rebuild)
     std::vector<WallLine> lines;
-    int spl = 1;                          // time steps per launch (1 or 2)
+    int spl = 1;                          // time steps per launch (1, 2 or 3)
     int ftw = 64, fth = 12;               // fused tile shape
     int nbulk = 0, nedge = 0;
     int nfint = 0, nfedge = 0;            // interior / edge tiles of the fused table
@@ -205,6 +218,7 @@ struct lbm13_batch {
     int cur = 0;                          // buffer holding the current state
     long long steps = 0;
     int graph_k = 0;
+    int graph_flip = 0;                   // 1 when a captured graph has an odd number of launches
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     std::string err;
@@ -313,6 +327,25 @@ int rebuild(lbm13_batch* b) {
     b->nfedge = (int)fedge.size();
     b->fused.insert(b->fused.end(), fedge.begin(), fedge.end());
     if ((int)b->fused.size() > b->L.tfmax) return fail(b, LBM13_EINVAL, "fused tile table overflow");
+    // Three steps per launch: every domain periodic on both axes, sides multiples
+    // of the tile and at least the tile + 12 (a region and its reach wrap at most
+    // once), planes within 32-bit byte offsets.  Flag 2, plus 4 where the region
+    // wraps (within six nodes of a side).
+    b->fused3.clear();
+    b->step3_ok = step3_shape(b->precision, b->ftw, b->fth);
+    for (int d = 0; d < b->count && b->step3_ok; ++d) {
+        const int* k = &b->sides_kind[4 * d];
+        const int nx = b->nx[d], ny = b->ny[d], tw = b->ftw, th = b->fth;
+        b->step3_ok = k[0] == LBM13_PERIODIC && k[2] == LBM13_PERIODIC && nx % tw == 0 && ny % th == 0 &&
+                      nx >= tw + 12 && ny >= th + 12 &&
+                      (13LL * b->L.plane[d] + 2LL * b->L.pitch[d] + 2) * es <= (long long)INT32_MAX;
+        for (int y0 = 0; y0 < ny && b->step3_ok; y0 += th)
+            for (int x0 = 0; x0 < nx; x0 += tw) {
+                const bool in = x0 >= 6 && x0 + tw + 6 <= nx && y0 >= 6 && y0 + th + 6 <= ny;
+                b->fused3.push_back(Tile{d, x0, y0, in ? 2 : 2 | 4});
+            }
+    }
+    if (!b->step3_ok) b->fused3.clear();
     b->lines.clear();
     for (int d = 0; d < b->count; ++d) {
         const int* k = &b->sides_kind[4 * d];
@@ -343,6 +376,11 @@ int rebuild(lbm13_batch* b) {
     e = hipMemcpyAsync(b->ws + b->L.tiles_fused, b->fused.data(), sizeof(Tile) * b->fused.size(),
                        hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hip_fail(b, e, "upload fused tile table");
+    if (!b->fused3.empty()) {
+        e = hipMemcpyAsync(b->ws + b->L.tiles_fused3, b->fused3.data(), sizeof(Tile) * b->fused3.size(),
+                           hipMemcpyHostToDevice, b->stream);
+        if (e != hipSuccess) return hip_fail(b, e, "upload three-step tile table");
+    }
     if (!b->lines.empty()) {
         e = hipMemcpyAsync(b->ws + b->L.lines, b->lines.data(), sizeof(WallLine) * b->lines.size(),
                            hipMemcpyHostToDevice, b->stream);
@@ -480,6 +518,30 @@ hipError_t launch_two_steps(lbm13_batch* b, int from, hipStream_t s) {
     return e;
 }
 
+template <typename R>
+hipError_t launch_three_steps(lbm13_batch* b, int from, hipStream_t s) {
+    const Tile* tiles = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_fused3);
+    return lbm13::launch_step3<R>(b->ftw, b->fth, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), tiles,
+                                  (int)b->fused3.size(), s);
+}
+
+// Enqueue n steps as launches of spl steps (then 2 and 1 for the remainder),
+// swapping the buffers once per launch; `launches` counts them.
+template <typename R>
+hipError_t enqueue_steps(lbm13_batch* b, long long n, int& from, hipStream_t s, long long& launches) {
+    while (n > 0) {
+        const int k = (b->spl == 3 && n >= 3) ? 3 : (b->spl >= 2 && n >= 2) ? 2 : 1;
+        const hipError_t e = k == 3 ? launch_three_steps<R>(b, from, s)
+                             : k == 2 ? launch_two_steps<R>(b, from, s)
+                                      : launch_one_step<R>(b, from, s);
+        if (e != hipSuccess) return e;
+        from = 1 - from;
+        n -= k;
+        ++launches;
+    }
+    return hipSuccess;
+}
+
 // Wall-layer side values of the kept state (after init, set_state, load).
 template <typename R>
 hipError_t fill_side(lbm13_batch* b, int only_dom) {
@@ -495,29 +557,19 @@ hipError_t fill_side_any(lbm13_batch* b, int only_dom) {
 }
 
 template <typename R>
-int do_step(lbm13_batch* b, int from) {
-    hipError_t e = launch_one_step<R>(b, from, b->stream);
-    if (e != hipSuccess) return hip_fail(b, e, "step launch");
-    return LBM13_OK;
-}
-
-template <typename R>
 int capture_graph(lbm13_batch* b, int parity) {
     hipError_t e;
     if (!b->capture_stream) {
         e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(b, e, "create capture stream");
     }
-    if (b->spl == 2 && (e = ensure_aux(b)) != hipSuccess) return hip_fail(b, e, "create auxiliary stream");
+    if (b->spl >= 2 && (e = ensure_aux(b)) != hipSuccess) return hip_fail(b, e, "create auxiliary stream");
     e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(b, e, "begin capture");
     int from = parity;
-    hipError_t le = hipSuccess;
-    for (int s = 0; s < b->graph_k && le == hipSuccess; s += b->spl) {
-        le = b->spl == 2 ? launch_two_steps<R>(b, from, b->capture_stream)
-                         : launch_one_step<R>(b, from, b->capture_stream);
-        from = 1 - from;
-    }
+    long long launches = 0;
+    const hipError_t le = enqueue_steps<R>(b, b->graph_k, from, b->capture_stream, launches);
+    b->graph_flip = (int)(launches & 1);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->capture_stream, &g);
     if (le != hipSuccess) {
@@ -538,6 +590,9 @@ int capture_graph(lbm13_batch* b, int parity) {
 
 template <typename R>
 int step_impl(lbm13_batch* b, long long n) {
+    if (b->spl == 3 && !b->step3_ok)
+        return fail(b, LBM13_EINVAL, "three steps per launch need domains periodic on both axes, sides multiples "
+                                     "of a three-step tile shape and at least the tile + 12");
     while (b->graph_k > 0 && n >= b->graph_k) {
         if (!b->gexec[b->cur]) {
             int st = capture_graph<R>(b, b->cur);
@@ -546,27 +601,20 @@ int step_impl(lbm13_batch* b, long long n) {
         hipError_t e = hipGraphLaunch(b->gexec[b->cur], b->stream);
         if (e != hipSuccess) return hip_fail(b, e, "graph launch");
         // each launch in the graph swaps the buffers once
-        if ((b->graph_k / b->spl) % 2 == 1) b->cur = 1 - b->cur;
+        if (b->graph_flip) b->cur = 1 - b->cur;
         n -= b->graph_k;
         b->steps += b->graph_k;
     }
-    if (b->spl == 2 && n >= 2) {
+    if (b->spl >= 2 && n >= 2) {
         hipError_t e = ensure_aux(b);
         if (e != hipSuccess) return hip_fail(b, e, "create auxiliary stream");
     }
-    while (b->spl == 2 && n >= 2) {
-        hipError_t e = launch_two_steps<R>(b, b->cur, b->stream);
-        if (e != hipSuccess) return hip_fail(b, e, "two-step launch");
-        b->cur = 1 - b->cur;
-        b->steps += 2;
-        n -= 2;
-    }
-    for (long long s = 0; s < n; ++s) {
-        int st = do_step<R>(b, b->cur);
-        if (st) return st;
-        b->cur = 1 - b->cur;
-        b->steps += 1;
-    }
+    int from = b->cur;
+    long long launches = 0;
+    const hipError_t e = enqueue_steps<R>(b, n, from, b->stream, launches);
+    if (e != hipSuccess) return hip_fail(b, e, "step launch");
+    b->cur = from;
+    b->steps += n;
     return LBM13_OK;
 }
 
@@ -586,7 +634,7 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
         return fail(b, LBM13_EDEVICE, "event create");
     const int keep_k = b->graph_k;
     b->graph_k = 0;
-    steps += steps & 1;  // an even count keeps two-step launches whole
+    steps = (steps + 5) / 6 * 6;  // a multiple of 6 keeps two- and three-step launches whole
     struct Cand {
         int spl, w, h, split;
     };
@@ -595,6 +643,8 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
     for (auto& f : kFusedShapes)
         if (fused_fits(b->precision, f[0], f[1]))
             for (int sp = 1; sp >= 0; --sp) cands.push_back(Cand{2, f[0], f[1], sp});
+    for (auto& f : kStep3Shapes[b->precision == LBM13_FP64 ? 0 : 1])
+        if (f[0] > 0) cands.push_back(Cand{3, f[0], f[1], b->split});
     float best = 1e30f;
     Cand pick{b->spl, b->spl == 2 ? b->ftw : b->tile_x, b->spl == 2 ? b->fth : b->tile_y, b->split};
     int st = LBM13_OK;
@@ -609,7 +659,8 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
             b->fth = c.h;
         }
         if ((st = rebuild(b))) break;
-        if ((st = step_impl<R>(b, 2))) break;
+        if (c.spl == 3 && !b->step3_ok) continue;  // not possible for these domains
+        if ((st = step_impl<R>(b, 6))) break;
         (void)hipEventRecord(e0, b->stream);
         if ((st = step_impl<R>(b, steps))) break;
         (void)hipEventRecord(e1, b->stream);
@@ -924,7 +975,7 @@ int lbm13_batch_set_fused_tile(lbm13_batch* b, int tile_x, int tile_y) {
 
 int lbm13_batch_set_steps_per_launch(lbm13_batch* b, int k) {
     if (!b) return LBM13_EINVAL;
-    if (k != 1 && k != 2) return fail(b, LBM13_EINVAL, "steps per launch must be 1 or 2");
+    if (k != 1 && k != 2 && k != 3) return fail(b, LBM13_EINVAL, "steps per launch must be 1, 2 or 3");
     drop_graphs(b);
     b->spl = k;
     return LBM13_OK;

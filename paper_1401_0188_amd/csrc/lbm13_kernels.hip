@@ -14,6 +14,8 @@
 // neighbouring wavefronts share cache lines in L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm13_device.h"
 
 namespace lbm13 {
@@ -776,6 +778,118 @@ __global__ __launch_bounds__(NT) void step2_interior_kernel(const R* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Three steps per launch on a domain periodic on both axes, whole tiles (flag
+// 2; with flag 4 the region wraps around the sides).  Phase 1 advances the
+// tile and a four-node halo from HBM and keeps population i only over the
+// window phase 2 reads (the tile and a two-node halo, shifted by -v_i); phase
+// 2 advances the tile and its two-node halo from LDS into registers, then,
+// after a barrier, keeps population i over the window phase 3 reads (the tile
+// shifted by -v_i) in the same LDS; phase 3 advances the tile and writes HBM.
+// Each node's arithmetic is the single-step kernel's.
+template <typename R, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void step3_kernel(const R* __restrict__ src, R* __restrict__ dst,
+                                                   const Dom<R>* __restrict__ doms,
+                                                   const Tile* __restrict__ tiles, int ntiles) {
+    constexpr int W1 = TW + 8, H1 = TH + 8, W2 = TW + 4, H2 = TH + 4;
+    constexpr int N1 = W1 * H1, N2 = W2 * H2, N3 = TW * TH;
+    constexpr int NI1 = (N1 + NT - 1) / NT, NI2 = (N2 + NT - 1) / NT;
+    constexpr int kLead = 2;  // keeps the window index of the population in slot 0 non-negative
+    __shared__ R lds[kLead + 13 * N2];
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const Tile tl = tiles[t];
+    const Dom<R>& D = doms[tl.dom];
+    const R* __restrict__ a = src + D.off;
+    R* __restrict__ o = dst + D.off;
+    const int P = D.pitch, S = D.plane;
+    const int tid = threadIdx.x;
+    constexpr int es = (int)sizeof(R);
+    const __amdgpu_buffer_rsrc_t in = buffer_rsrc(a - (2 * P + 2), (unsigned)((13 * S + 2 * P + 2) * es));
+    const bool wraps = tl.flags & 4;
+
+    // Phase 1: region (x0 - 4, y0 - 4) + [0, W1) x [0, H1); all loads issued first.
+    R g[NI1][13];
+    int l1x[NI1], l1y[NI1];
+#pragma unroll
+    for (int k = 0; k < NI1; ++k) {
+        const int r = min(tid + k * NT, N1 - 1);
+        l1x[k] = r % W1;
+        l1y[k] = r / W1;
+        const int X = tl.x0 - 4 + l1x[k], Y = tl.y0 - 4 + l1y[k];
+        if (wraps) {
+            int xs[5], ys[5];  // X + 2 - v and Y + 2 - v wrapped once, v = 0..4
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                xs[v] = wrap(X + 2 - v, D.nx);
+                ys[v] = wrap(Y + 2 - v, D.ny) * P;
+            }
+#pragma unroll
+            for (int i = 0; i < 13; ++i)
+                g[k][i] = buffer_load<R>(in, (unsigned)((ys[kVY[i] + 2] + xs[kVX[i] + 2]) * es),
+                                         (unsigned)((i * S + 2 * P + 2) * es));
+        } else {
+            const unsigned c = (unsigned)((Y * P + X) * es);
+#pragma unroll
+            for (int i = 0; i < 13; ++i)
+                g[k][i] = buffer_load<R>(in, c, (unsigned)((i * S + (2 - kVY[i]) * P + 2 - kVX[i]) * es));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NI1; ++k) {
+        if (D.collide) collide(g[k], D);
+        if (tid + k * NT < N1) {
+            const int lx = l1x[k], ly = l1y[k], base = ly * W2 + lx;
+#define LBM13_WINDOW1(I)                                                                                   \
+    if ((unsigned)(lx - 2 + kVX[I]) < (unsigned)W2 && (unsigned)(ly - 2 + kVY[I]) < (unsigned)H2)          \
+        lds[base + (kLead + Slot<I>::value * N2 + (kVY[I] - 2) * W2 + kVX[I] - 2)] = g[k][I];
+            LBM13_WINDOW1(0) LBM13_WINDOW1(1) LBM13_WINDOW1(2) LBM13_WINDOW1(3) LBM13_WINDOW1(4)
+            LBM13_WINDOW1(5) LBM13_WINDOW1(6) LBM13_WINDOW1(7) LBM13_WINDOW1(8) LBM13_WINDOW1(9)
+            LBM13_WINDOW1(10) LBM13_WINDOW1(11) LBM13_WINDOW1(12)
+#undef LBM13_WINDOW1
+        }
+    }
+    __syncthreads();
+
+    // Phase 2: region (x0 - 2, y0 - 2) + [0, W2) x [0, H2), node r reads index r of every slot.
+    R h[NI2][13];
+#pragma unroll
+    for (int k = 0; k < NI2; ++k) {
+        const int r = min(tid + k * NT, N2 - 1);
+#pragma unroll
+        for (int i = 0; i < 13; ++i) h[k][i] = lds[kLead + ((i + 3) % 13) * N2 + r];
+        if (D.collide) collide(h[k], D);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NI2; ++k) {
+        const int r = tid + k * NT;
+        if (r < N2) {
+            const int lx = r % W2, ly = r / W2, base = ly * TW + lx;
+#define LBM13_WINDOW2(I)                                                                                   \
+    if ((unsigned)(lx - 2 + kVX[I]) < (unsigned)TW && (unsigned)(ly - 2 + kVY[I]) < (unsigned)TH)          \
+        lds[base + (kLead + Slot<I>::value * N3 + (kVY[I] - 2) * TW + kVX[I] - 2)] = h[k][I];
+            LBM13_WINDOW2(0) LBM13_WINDOW2(1) LBM13_WINDOW2(2) LBM13_WINDOW2(3) LBM13_WINDOW2(4)
+            LBM13_WINDOW2(5) LBM13_WINDOW2(6) LBM13_WINDOW2(7) LBM13_WINDOW2(8) LBM13_WINDOW2(9)
+            LBM13_WINDOW2(10) LBM13_WINDOW2(11) LBM13_WINDOW2(12)
+#undef LBM13_WINDOW2
+        }
+    }
+    __syncthreads();
+
+    // Phase 3: the tile, node r reads index r of every slot.
+    const __amdgpu_buffer_rsrc_t out = buffer_rsrc(o, (unsigned)(13 * S * es));
+    for (int r = tid; r < N3; r += NT) {
+        const int tx = r % TW, ty = r / TW;
+        const unsigned c = (unsigned)(((tl.y0 + ty) * P + tl.x0 + tx) * es);
+        R q[13];
+#pragma unroll
+        for (int i = 0; i < 13; ++i) q[i] = lds[kLead + ((i + 3) % 13) * N3 + r];
+        if (D.collide) collide(q, D);
+#pragma unroll
+        for (int i = 0; i < 13; ++i) buffer_store_nt<R>(q[i], out, c, (unsigned)(i * S * es));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Initial state: g = f^eq(rho, j = rho u, E = T + 13/2 |u|^2) - f^rest, built in
 // FP64 from the equilibrium moments (eq d2q13-moments-equil) and M^T D^-1, then
 // one collision in the working precision.
@@ -1281,6 +1395,30 @@ hipError_t launch_step2(int tw, int th, const R* src, R* dst, const Dom<R>* doms
     return hipErrorInvalidValue;
 }
 
+// Three steps per launch (domains periodic on both axes, whole tiles).
+template <typename R>
+hipError_t launch_step3(int tw, int th, const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int ntiles,
+                        hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+#define LBM13_STEP3(T, TW, TH)                                                                                 \
+    if constexpr (std::is_same<R, T>::value) {                                                                 \
+        if (tw == TW && th == TH) {                                                                            \
+            constexpr int NT = TW * TH >= 1024 ? 512 : 256;                                                    \
+            step3_kernel<R, TW, TH, NT><<<ntiles, NT, 0, s>>>(src, dst, doms, tiles, ntiles);                 \
+            return hipGetLastError();                                                                          \
+        }                                                                                                      \
+    }
+    LBM13_STEP3(float, 64, 16)
+    LBM13_STEP3(float, 32, 32)
+    LBM13_STEP3(float, 64, 8)
+    LBM13_STEP3(float, 32, 16)
+    LBM13_STEP3(double, 64, 8)
+    LBM13_STEP3(double, 32, 16)
+    LBM13_STEP3(double, 32, 8)
+#undef LBM13_STEP3
+    return hipErrorInvalidValue;
+}
+
 template <typename R>
 hipError_t launch_side_fill(const R* src, const Dom<R>* doms, const WallLine* lines, int nlines, R* side, int buf,
                             int only_dom, hipStream_t s) {
@@ -1324,6 +1462,7 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
                                        R*, int, hipStream_t);                                                     \
     template hipError_t launch_step2<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int,     \
                                         hipStream_t);                                                             \
+    template hipError_t launch_step3<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, hipStream_t);   \
     template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, int,          \
                                             hipStream_t);                                                         \
     template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, R*,     \

@@ -220,6 +220,8 @@ def launch_candidates(lbm13, precision):
     for ft in lbm13.FUSED_TILE_SHAPES[precision]:
         for on in (True, False):
             out.append(dict(spl=2, fused_tile=ft, interior_kernel=on))
+    for ft in lbm13.STEP3_TILE_SHAPES[precision]:
+        out.append(dict(spl=3, fused_tile=ft, interior_kernel=True))
     return out
 
 
@@ -722,6 +724,78 @@ def test_full_size_wave_rates_match_linear_theory(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_three_steps_per_launch_periodic(precision):
+    """Three steps per launch on periodic domains, every three-step tile shape,
+    with forces, a remainder step and graph replay, against the oracle."""
+    lbm13 = _lb()
+    nx, ny = 128, 96
+    fields = workloads.shear_acoustic(nx, ny)
+    for ft in lbm13.STEP3_TILE_SHAPES[precision]:
+        for graph in (0, 10):
+            say("three-step tile %s precision %d graph %d" % (ft, precision, graph))
+            lat, gs, gm, fs, om, *_ = run_both(nx, ny, fields, 31, spl=3, fused_tile=ft, graph=graph,
+                                               precision=precision, F0=(1e-5, -2e-5), g=(0.0, -1e-3))
+            assert lat.launch_config()["steps_per_launch"] == 3
+            if precision == 0:
+                assert_fp64(gs, gm, fs, om)
+            else:
+                assert_fp32(gm, om)
+            lat.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_three_steps_per_launch_matches_single_steps(precision):
+    """With collisions off, 30 steps in three-step launches are exactly 30
+    streaming steps (the LDS windows hold exactly the values the gathers
+    need); with collisions on they agree with single-step launches to
+    rounding (the collision is the same code, contracted by the compiler in
+    each kernel's context)."""
+    lbm13 = _lb()
+    nx, ny = 192, 64
+    rng = np.random.default_rng(11)
+    fields = (1 + 0.01 * rng.standard_normal((ny, nx)), 0.01 * rng.standard_normal((ny, nx)),
+              0.01 * rng.standard_normal((ny, nx)), -2 + 0.01 * rng.standard_normal((ny, nx)))
+    for collide in (0, 1):
+        states = []
+        for spl in (1, 3):
+            say("three-step vs single-step precision %d, collide %d, spl %d" % (precision, collide, spl))
+            lat = lbm13.Lattice(nx, ny, precision)
+            lat.set_fused_tile(*lbm13.STEP3_TILE_SHAPES[precision][0])
+            lat.set_steps_per_launch(spl)
+            lat.set_params(g=(1e-4, -1e-4), collide=collide)
+            lat.init_moments(*fields)
+            lat.step(30)
+            states.append(lat.get_state().cpu().numpy())
+            lat.destroy()
+        if collide == 0:
+            assert np.array_equal(states[0], states[1])
+        else:
+            err = np.abs(states[0] - states[1]).max() / np.abs(states[0]).max()
+            assert err <= (1e-14 if precision == 0 else 1e-6), err
+
+
+def test_three_steps_per_launch_rejects_walls_and_ragged_sides():
+    lbm13 = _lb()
+    say("three-step feasibility errors")
+    lat = lbm13.Lattice(128, 96, lbm13.FP32_DEV)
+    lat.set_fused_tile(64, 16)
+    lat.set_steps_per_launch(3)
+    lat.set_params(sides=lbm13.make_sides((2, 2, 0, 0), (0, 0, 0, 0), (-1.99, -2.01, 0, 0)))
+    lat.init_moments(*workloads.rest_fields(128, 96))
+    with pytest.raises(lbm13.LBM13Error):
+        lat.step(3)
+    lat.destroy()
+    lat = lbm13.Lattice(130, 96, lbm13.FP32_DEV)  # 130 is not a multiple of 64
+    lat.set_fused_tile(64, 16)
+    lat.set_steps_per_launch(3)
+    lat.set_params()
+    lat.init_moments(*workloads.rest_fields(130, 96))
+    with pytest.raises(lbm13.LBM13Error):
+        lat.step(3)
+    lat.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_interior_kernel_switch_is_bit_exact(precision):
     """Two-step launches with the interior tiles on their own kernel (run
     concurrently with the general kernel) and with every tile on the general
@@ -747,14 +821,14 @@ def test_interior_kernel_switch_is_bit_exact(precision):
 
 def test_autotune_considers_two_step_launches():
     lbm13 = _lb()
-    say("autotune with two-step candidates")
+    say("autotune with two- and three-step candidates")
     fields = workloads.shear_acoustic(512)
     lat = lbm13.Lattice(512, 512, lbm13.FP32_DEV)
     lat.set_params()
     lat.init_moments(*fields)
     lat.autotune(6)
     cfg = lat.launch_config()
-    assert cfg["steps_per_launch"] in (1, 2)
+    assert cfg["steps_per_launch"] in (1, 2, 3)
     n = lat.steps_done()
     lat.step(7)
     po = oracle.params()
