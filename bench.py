@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 BENCH_CONFIG = {1: dict(spl=2, fused_tile=(32, 32), tile=(64, 8)),
                 0: dict(spl=2, fused_tile=(32, 16), tile=(64, 8))}
 BENCH_TILE = BENCH_CONFIG[1]["tile"]
-GRAPH_K = 100                 # steps per captured HIP graph
+GRAPH_K = 120                 # steps per captured HIP graph (a multiple of 2 and 3: whole multi-step launches)
 BYTES_PER_LU = {0: 208, 1: 104}  # 13 loads + 13 stores of populations, FP64 / FP32
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E
 METRIC = "MLUPS and % of HBM roofline, FP32/batched vs plain FP64 GPU at stated error"
@@ -365,7 +365,7 @@ def main_batched(args, copy_gbps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=2040)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="wave4096", choices=["wave4096", "cavities64", "channels128"])
     ap.add_argument("--size", type=int, default=4096, help="side of the periodic wave (wave4096)")
