@@ -439,12 +439,16 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
     D->gx_d = p->g[0];
     D->gy_d = p->g[1];
     const double ke = p->s_eps / 42196.0, kv = p->s_varpi / 548.0;
-    D->ke = R(ke);
-    D->ker = R(-ke * dv->c_eps_rho);
-    D->keE = R(-ke * p->c_epsE);
-    D->kv = R(kv);
-    D->kvr = R(-kv * p->c_varpi_rho);
-    D->kvE = R(-kv * p->c_varpi_E);
+    {
+        // rows of M over the classes (rest, |v|^2 = 1, 2, 4) for E, eps, varpi
+        // (the rho row is 1 on every class)
+        const double Er[4] = {-28, -15, -2, 24}, er[4] = {140, -2, -67, 34}, vr[4] = {-12, 8, -6, 1};
+        for (int j = 0; j < 4; ++j) {
+            D->aeps[j] = R(ke * (er[j] - dv->c_eps_rho - p->c_epsE * Er[j]));
+            D->avp[j] = R(kv * (vr[j] - p->c_varpi_rho - p->c_varpi_E * Er[j]));
+            D->eQ[j] = R(-Er[j] * p->Q_E / 4004.0);
+        }
+    }
     D->kX = R(p->s_XX / 68.0);
     D->kY = R(p->s_XX / 4.0);
     D->kXe = R(p->s_XXe / 68.0);
@@ -454,7 +458,6 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
     D->fjy = R(-F0y / 14.0);
     D->gjx = R(-p->g[0] / 14.0);
     D->gjy = R(-p->g[1] / 14.0);
-    D->qE = R(p->Q_E / 4004.0);
     D->QE = R(p->Q_E);
     D->QE_d = p->Q_E;
     for (int w = 0; w < 4; ++w) {

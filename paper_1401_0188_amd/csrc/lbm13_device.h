@@ -35,13 +35,17 @@ struct alignas(16) Dom {
     R a1, h1, k1, a2, h2, k2;
     // body force F = F0 + g rho' (F0 already holds F0 + g (1 - rho0)); energy source
     R F0x, F0y, gx, gy;
-    R qE;  // Q_E / 4004: the energy source divided by the norm of the E moment
     R QE;  // Q_E: the kept post-collision state carries E(t) + Q_E
     // relaxation folded with the norms D_k for the collision:
-    //   s_eps (eps - eps^eq) / 42196 = ke eps + ker rho' + keE E'  (likewise kv.. for varpi),
+    //   s_eps (eps - eps^eq) / 42196 = sum_j aeps[j] (g0, S1, S2, S3)_j and
+    //   s_varpi (varpi - varpi^eq) / 548 = sum_j avp[j] (g0, S1, S2, S3)_j, with
+    //   S1, S2, S3 the sums over the classes |v|^2 = 1, 2, 4 (both are linear in
+    //   the populations); eQ[c] = -M_E,c Q_E / 4004, the energy source as
+    //   Delta_E = -Q_E for the rest population and the three classes;
     //   kX = s_XX / 68, kY = s_XX / 4, kXe = s_XXe / 68, kq = s_q / 20, kr = s_r / 70,
     //   -F / 14 = fjx + gjx rho' (and y)
-    R ke, ker, keE, kv, kvr, kvE;
+    R aeps[4], avp[4];
+    R eQ[4];
     R kX, kY, kXe, kq, kr;
     R fjx, fjy, gjx, gjy;
     // walls: tangential velocity, E_W - E0 for temperature walls

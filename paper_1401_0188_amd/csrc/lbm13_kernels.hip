@@ -76,8 +76,6 @@ __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
     const R S1 = s13 + s24, S2 = s57 + s68, S3 = s9 + s10;
     const R rho = g[0] + S1 + S2 + S3;  // rho - 1
     const R E = R(-28) * g[0] - R(15) * S1 - R(2) * S2 + R(24) * S3;  // E - E0
-    const R eps = R(140) * g[0] - R(2) * S1 - R(67) * S2 + R(34) * S3;
-    const R vp = R(-12) * g[0] + R(8) * S1 - R(6) * S2 + S3;
     const R A1 = s13 - s24, A3 = s9 - s10;
     const R XX = A1 + R(4) * A3;
     const R XY = s57 - s68;
@@ -92,9 +90,7 @@ __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
     const R inv_rho = reciprocal(R(1) + rho);
     const R fq = D.a1 + D.h1 * rho + D.k1 * E;
     const R fr = D.a2 + D.h2 * rho + D.k2 * E;
-    // Delta_k / D_k for the even non-conserved moments
-    const R aeps = D.ke * eps + D.ker * rho + D.keE * E;
-    const R avp = D.kv * vp + D.kvr * rho + D.kvE * E;
+    // Delta_k / D_k for the anisotropic even moments
     const R aXX = D.kX * (XX - (jx * jx - jy * jy) * inv_rho);
     const R aXY = D.kY * (XY - jx * jy * inv_rho);
     const R aXXe = D.kXe * XXe;
@@ -103,16 +99,20 @@ __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
     const R bqx = D.kq * (qx - jx * fq), bqy = D.kq * (qy - jy * fq);
     const R brx = D.kr * (rx - jx * fr), bry = D.kr * (ry - jy * fr);
 
-    // the energy source enters as Delta_E = -Q_E (sec. 9)
-    const R aQ = D.qE;
-    const R e0 = R(140) * aeps - R(12) * avp + R(28) * aQ;
-    const R ec1 = R(-2) * aeps + R(8) * avp + R(15) * aQ;
+    // isotropic even part: eps and varpi relaxed (each a linear form of the
+    // class sums), mapped back by the integer rows of M so that the update
+    // keeps sum g and the E moment exactly; the energy source enters as
+    // Delta_E = -Q_E (sec. 9)
+    const R aeps = D.aeps[0] * g[0] + D.aeps[1] * S1 + D.aeps[2] * S2 + D.aeps[3] * S3;
+    const R avp = D.avp[0] * g[0] + D.avp[1] * S1 + D.avp[2] * S2 + D.avp[3] * S3;
+    const R e0 = R(140) * aeps - R(12) * avp + D.eQ[0];
+    const R ec1 = R(-2) * aeps + R(8) * avp + D.eQ[1];
+    const R ec5 = R(-67) * aeps - R(6) * avp + D.eQ[2];
+    const R ec9 = R(34) * aeps + avp + D.eQ[3];
     const R e1 = ec1 + aXX - R(4) * aXXe;
     const R e2 = ec1 - aXX + R(4) * aXXe;
-    const R ec5 = R(-67) * aeps - R(6) * avp + R(2) * aQ;
     const R e5 = ec5 + aXY;
     const R e6 = ec5 - aXY;
-    const R ec9 = R(34) * aeps + avp - R(24) * aQ;
     const R e9 = ec9 + R(4) * aXX + aXXe;
     const R e10 = ec9 - R(4) * aXX - aXXe;
     const R o1 = bjx - R(2) * bqx + R(4) * brx;
