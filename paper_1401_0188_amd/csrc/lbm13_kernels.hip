@@ -503,6 +503,14 @@ __global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R*
 // re-read from L2 by neighbouring tiles), for (TW+4)(TH+4)/(TW TH) times the
 // phase-1 collision work.  Wall-layer densities of step t + 1 are kept in LDS
 // for phase 2's wall states.
+// Waves per SIMD that a workgroup of nt threads with lds_bytes of LDS allows
+// (160 KB of LDS and at most 8 waves per SIMD on a CU of 4 SIMDs).  FP32
+// kernels ask the compiler for the registers of that occupancy.
+constexpr int lds_waves_per_eu(int lds_bytes, int nt) {
+    const int w = (163840 / lds_bytes) * nt / 256;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 __device__ __forceinline__ int pmod(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
@@ -547,7 +555,9 @@ __device__ __forceinline__ void buffer_store_nt<double>(double v, __amdgpu_buffe
 }
 
 template <typename R, int TW, int TH, int NT>
-__global__ __launch_bounds__(NT) void step2_kernel(const R* __restrict__ src, R* __restrict__ dst,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    sizeof(R) == 4 ? lds_waves_per_eu((13 * (TW + 4) * (TH + 4) + 6 * (TW + TH + 8)) * (int)sizeof(R), NT) : 1)))
+void step2_kernel(const R* __restrict__ src, R* __restrict__ dst,
                                                    const Dom<R>* __restrict__ doms,
                                                    const Tile* __restrict__ tiles, int ntiles,
                                                    R* __restrict__ side, int from) {
@@ -582,8 +592,8 @@ __global__ __launch_bounds__(NT) void step2_kernel(const R* __restrict__ src, R*
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             const int r = tid + k * NT;
-            if (D.collide) collide(h[k], D);
             if (r < RW * RH) {
+                if (D.collide) collide(h[k], D);
 #pragma unroll
                 for (int i = 0; i < 13; ++i) lds[i * RH * RW + r] = h[k][i];
             }
@@ -698,7 +708,9 @@ struct Slot {  // LDS slot of population I: velocity 10, (0, 2), takes slot 0
 };
 
 template <typename R, int TW, int TH, int NT>
-__global__ __launch_bounds__(NT) void step2_interior_kernel(const R* __restrict__ src, R* __restrict__ dst,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    sizeof(R) == 4 ? lds_waves_per_eu((2 + 13 * TW * TH) * (int)sizeof(R), NT) : 1)))
+void step2_interior_kernel(const R* __restrict__ src, R* __restrict__ dst,
                                                            const Dom<R>* __restrict__ doms,
                                                            const Tile* __restrict__ tiles, int ntiles) {
     constexpr int RW = TW + 4, RH = TH + 4, N = TW * TH;
@@ -737,8 +749,8 @@ __global__ __launch_bounds__(NT) void step2_interior_kernel(const R* __restrict_
     }
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
-        if (D.collide) collide(g[k], D);
         if (tid + k * NT < RW * RH) {
+            if (D.collide) collide(g[k], D);
             const int lx = lxs[k], ly = lys[k], base = ly * TW + lx;
 #define LBM13_WINDOW_STORE(I)                                                                              \
     if ((unsigned)(lx - 2 + kVX[I]) < (unsigned)TW && (unsigned)(ly - 2 + kVY[I]) < (unsigned)TH)          \
@@ -785,9 +797,14 @@ __global__ __launch_bounds__(NT) void step2_interior_kernel(const R* __restrict_
 // 2 advances the tile and its two-node halo from LDS into registers, then,
 // after a barrier, keeps population i over the window phase 3 reads (the tile
 // shifted by -v_i) in the same LDS; phase 3 advances the tile and writes HBM.
-// Each node's arithmetic is the single-step kernel's.
+// Each node's arithmetic is the single-step kernel's.  Node slots past a
+// region's end collide nothing, so whole waves with no node in a slot skip it
+// (their phase-1 loads stay: they re-read the region's last node).  FP32 uses
+// one thread per tile node, with the registers of the occupancy the LDS
+// allows (two 1024-thread workgroups: eight waves per SIMD).
 template <typename R, int TW, int TH, int NT>
-__global__ __launch_bounds__(NT) void step3_kernel(const R* __restrict__ src, R* __restrict__ dst,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    sizeof(R) == 4 ? lds_waves_per_eu((2 + 13 * (TW + 4) * (TH + 4)) * (int)sizeof(R), NT) : 1))) void step3_kernel(const R* __restrict__ src, R* __restrict__ dst,
                                                    const Dom<R>* __restrict__ doms,
                                                    const Tile* __restrict__ tiles, int ntiles) {
     constexpr int W1 = TW + 8, H1 = TH + 8, W2 = TW + 4, H2 = TH + 4;
@@ -835,8 +852,8 @@ __global__ __launch_bounds__(NT) void step3_kernel(const R* __restrict__ src, R*
     }
 #pragma unroll
     for (int k = 0; k < NI1; ++k) {
-        if (D.collide) collide(g[k], D);
         if (tid + k * NT < N1) {
+            if (D.collide) collide(g[k], D);
             const int lx = l1x[k], ly = l1y[k], base = ly * W2 + lx;
 #define LBM13_WINDOW1(I)                                                                                   \
     if ((unsigned)(lx - 2 + kVX[I]) < (unsigned)W2 && (unsigned)(ly - 2 + kVY[I]) < (unsigned)H2)          \
@@ -853,10 +870,12 @@ __global__ __launch_bounds__(NT) void step3_kernel(const R* __restrict__ src, R*
     R h[NI2][13];
 #pragma unroll
     for (int k = 0; k < NI2; ++k) {
-        const int r = min(tid + k * NT, N2 - 1);
+        const int r = tid + k * NT;
+        if (r < N2) {
 #pragma unroll
-        for (int i = 0; i < 13; ++i) h[k][i] = lds[kLead + ((i + 3) % 13) * N2 + r];
-        if (D.collide) collide(h[k], D);
+            for (int i = 0; i < 13; ++i) h[k][i] = lds[kLead + ((i + 3) % 13) * N2 + r];
+            if (D.collide) collide(h[k], D);
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -1370,14 +1389,18 @@ hipError_t launch_fourier(int tile_x, int tile_y, const R* src, const Dom<R>* do
 }
 
 // Two steps per launch: interior tiles tiles[0, nint), then tiles touching a
-// wall or a periodic wrap tiles[nint, nint + nedge).
+// wall or a periodic wrap tiles[nint, nint + nedge).  FP32 takes one thread per
+// tile node for tiles of 512 and 1024 nodes with registers capped at 64 (eight
+// waves per SIMD where the LDS allows it); node slots past the region's end
+// collide nothing.
 template <typename R>
 hipError_t launch_step2(int tw, int th, const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int nint,
                         int nedge, R* side, int from, hipStream_t s) {
 #define LBM13_FUSED(TW, TH)                                                                                    \
     if (tw == TW && th == TH) {                                                                                \
         static_assert(FusedFits<R, TW, TH>::value, "two-step region exceeds LDS");                             \
-        constexpr int NT = TW * TH >= 1024 ? 512 : 256;                                                        \
+        constexpr int NT = sizeof(R) == 4 ? (TW * TH >= 1024 ? 1024 : TW * TH >= 512 ? 512 : 256)              \
+                                          : (TW * TH >= 1024 ? 512 : 256);                                     \
         if (nint > 0) step2_interior_kernel<R, TW, TH, NT><<<nint, NT, 0, s>>>(src, dst, doms, tiles, nint);  \
         if (nedge > 0)                                                                                         \
             step2_kernel<R, TW, TH, NT><<<nedge, NT, 0, s>>>(src, dst, doms, tiles + nint, nedge, side, from); \
@@ -1403,7 +1426,7 @@ hipError_t launch_step3(int tw, int th, const R* src, R* dst, const Dom<R>* doms
 #define LBM13_STEP3(T, TW, TH)                                                                                 \
     if constexpr (std::is_same<R, T>::value) {                                                                 \
         if (tw == TW && th == TH) {                                                                            \
-            constexpr int NT = TW * TH >= 1024 ? 512 : 256;                                                    \
+            constexpr int NT = sizeof(R) == 4 ? (TW * TH >= 1024 ? 1024 : 512) : (TW * TH >= 1024 ? 512 : 256); \
             step3_kernel<R, TW, TH, NT><<<ntiles, NT, 0, s>>>(src, dst, doms, tiles, ntiles);                 \
             return hipGetLastError();                                                                          \
         }                                                                                                      \
