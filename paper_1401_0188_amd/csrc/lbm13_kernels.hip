@@ -504,8 +504,8 @@ __global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R*
 // phase-1 collision work.  Wall-layer densities of step t + 1 are kept in LDS
 // for phase 2's wall states.
 // Waves per SIMD that a workgroup of nt threads with lds_bytes of LDS allows
-// (160 KB of LDS and at most 8 waves per SIMD on a CU of 4 SIMDs).  FP32
-// kernels ask the compiler for the registers of that occupancy.
+// (160 KB of LDS and at most 8 waves per SIMD on a CU of 4 SIMDs); the
+// multi-step kernels ask the compiler for the registers of that occupancy.
 constexpr int lds_waves_per_eu(int lds_bytes, int nt) {
     const int w = (163840 / lds_bytes) * nt / 256;
     return w < 1 ? 1 : (w > 8 ? 8 : w);
@@ -799,12 +799,13 @@ void step2_interior_kernel(const R* __restrict__ src, R* __restrict__ dst,
 // shifted by -v_i) in the same LDS; phase 3 advances the tile and writes HBM.
 // Each node's arithmetic is the single-step kernel's.  Node slots past a
 // region's end collide nothing, so whole waves with no node in a slot skip it
-// (their phase-1 loads stay: they re-read the region's last node).  FP32 uses
-// one thread per tile node, with the registers of the occupancy the LDS
-// allows (two 1024-thread workgroups: eight waves per SIMD).
+// (their phase-1 loads stay: they re-read the region's last node).  Tiles of
+// up to 1024 (FP32) or 512 (FP64) nodes take one thread per node, with the
+// registers of the occupancy the LDS allows (FP32 64x16: two 1024-thread
+// workgroups, eight waves per SIMD; FP64 32x16: two 512-thread workgroups).
 template <typename R, int TW, int TH, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
-    sizeof(R) == 4 ? lds_waves_per_eu((2 + 13 * (TW + 4) * (TH + 4)) * (int)sizeof(R), NT) : 1))) void step3_kernel(const R* __restrict__ src, R* __restrict__ dst,
+    lds_waves_per_eu((2 + 13 * (TW + 4) * (TH + 4)) * (int)sizeof(R), NT)))) void step3_kernel(const R* __restrict__ src, R* __restrict__ dst,
                                                    const Dom<R>* __restrict__ doms,
                                                    const Tile* __restrict__ tiles, int ntiles) {
     constexpr int W1 = TW + 8, H1 = TH + 8, W2 = TW + 4, H2 = TH + 4;
@@ -1426,7 +1427,7 @@ hipError_t launch_step3(int tw, int th, const R* src, R* dst, const Dom<R>* doms
 #define LBM13_STEP3(T, TW, TH)                                                                                 \
     if constexpr (std::is_same<R, T>::value) {                                                                 \
         if (tw == TW && th == TH) {                                                                            \
-            constexpr int NT = sizeof(R) == 4 ? (TW * TH >= 1024 ? 1024 : 512) : (TW * TH >= 1024 ? 512 : 256); \
+            constexpr int NT = sizeof(R) == 4 ? (TW * TH >= 1024 ? 1024 : 512) : (TW * TH >= 512 ? 512 : 256); \
             step3_kernel<R, TW, TH, NT><<<ntiles, NT, 0, s>>>(src, dst, doms, tiles, ntiles);                 \
             return hipGetLastError();                                                                          \
         }                                                                                                      \
