@@ -193,7 +193,8 @@ long long lbm13_steps_done(const lbm13_ctx *ctx);
 int lbm13_set_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
 
 /* Time every supported launch configuration (single-step tile shapes,
- * two-steps-per-launch tile shapes with and without the interior kernel) for
+ * two-steps-per-launch tile shapes with and without the interior kernel,
+ * three-steps-per-launch tile shapes) for
  * `steps` steps on the current state
  * (the state is advanced, so save it first if needed) and keep the fastest.
  * Writes the chosen kernel's tile shape to tile_x/tile_y when not NULL (see
@@ -213,12 +214,14 @@ int lbm13_use_graph(lbm13_ctx *ctx, int k);
  * tile and a two-node halo by one step into LDS, then the tile by a second
  * step; same arithmetic per node, so results equal two single steps, with
  * about half the HBM traffic per step) or 3 (tile + 4-node halo, then tile +
- * 2-node halo, then the tile: a third of the HBM traffic per step; only for
- * domains periodic on both axes whose sides are multiples of the two-step
- * tile, which must be a three-step shape: FP32 (64, 16), (32, 32), (64, 8),
- * (32, 16); FP64 (64, 8), (32, 16), (32, 8); lbm13_step returns EINVAL
- * otherwise).  A remainder of lbm13_step(n) is done by shorter launches.
- * EINVAL for other values. */
+ * 2-node halo, then the tile: a third of the HBM traffic per step; any sides
+ * and walls, wall states of the intermediate steps from the levels kept in
+ * LDS; tiles far from walls and ragged edges run a kernel that keeps only the
+ * windows the next level reads, the others keep each level's whole region;
+ * the two-step tile must be a three-step shape: FP32 (64, 16), (32, 32),
+ * (64, 8), (32, 16); FP64 (64, 8), (32, 16), (32, 8); lbm13_step returns
+ * EINVAL otherwise).  A remainder of lbm13_step(n) is done by shorter
+ * launches.  EINVAL for other values. */
 int lbm13_set_steps_per_launch(lbm13_ctx *ctx, int k);
 
 /* Tile of the two-steps-per-launch kernels: (64, 16), (64, 12), (64, 8),

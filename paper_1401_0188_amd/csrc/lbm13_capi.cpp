@@ -37,7 +37,7 @@ template <typename R>
 hipError_t launch_fourier(int, int, const R*, const Dom<R>*, int, int, const Tile*, int, int, double*, double*,
                           hipStream_t);
 template <typename R>
-hipError_t launch_step3(int, int, const R*, R*, const Dom<R>*, const Tile*, int, hipStream_t);
+hipError_t launch_step3(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int, hipStream_t);
 template <typename R>
 hipError_t launch_init(int, int, R*, const Dom<R>*, int, const double*, const double*, const double*, const double*,
                        const double*, hipStream_t);
@@ -213,6 +213,7 @@ struct lbm13_batch {
     int ftw = 64, fth = 12;               // fused tile shape
     int nbulk = 0, nedge = 0;
     int nfint = 0, nfedge = 0;            // interior / edge tiles of the fused table
+    int n3int = 0, n3edge = 0;            // interior / edge tiles of the three-step table
     int split = 1;                        // 1: interior tiles run the compact-LDS kernel
     int tile_x = 64, tile_y = 8;
     int cur = 0;                          // buffer holding the current state
@@ -327,25 +328,32 @@ int rebuild(lbm13_batch* b) {
     b->nfedge = (int)fedge.size();
     b->fused.insert(b->fused.end(), fedge.begin(), fedge.end());
     if ((int)b->fused.size() > b->L.tfmax) return fail(b, LBM13_EINVAL, "fused tile table overflow");
-    // Three steps per launch: every domain periodic on both axes, sides multiples
-    // of the tile and at least the tile + 12 (a region and its reach wrap at most
-    // once), planes within 32-bit byte offsets.  Flag 2, plus 4 where the region
-    // wraps (within six nodes of a side).
+    // Three steps per launch (a three-step tile shape).  Interior tiles run
+    // step3_kernel: whole tiles whose region and its reach (six nodes around the
+    // tile) stay at least two nodes from every wall, on a periodic axis a side
+    // of at least the tile + 12 (the region and its reach wrap at most once),
+    // planes within 32-bit byte offsets; flag 2, plus 4 where the region wraps.
+    // The other tiles run step3_wall_kernel.
     b->fused3.clear();
     b->step3_ok = step3_shape(b->precision, b->ftw, b->fth);
+    std::vector<Tile> f3edge;
     for (int d = 0; d < b->count && b->step3_ok; ++d) {
         const int* k = &b->sides_kind[4 * d];
         const int nx = b->nx[d], ny = b->ny[d], tw = b->ftw, th = b->fth;
-        b->step3_ok = k[0] == LBM13_PERIODIC && k[2] == LBM13_PERIODIC && nx % tw == 0 && ny % th == 0 &&
-                      nx >= tw + 12 && ny >= th + 12 &&
-                      (13LL * b->L.plane[d] + 2LL * b->L.pitch[d] + 2) * es <= (long long)INT32_MAX;
-        for (int y0 = 0; y0 < ny && b->step3_ok; y0 += th)
+        const bool small = (13LL * b->L.plane[d] + 2LL * b->L.pitch[d] + 2) * es <= (long long)INT32_MAX;
+        for (int y0 = 0; y0 < ny; y0 += th)
             for (int x0 = 0; x0 < nx; x0 += tw) {
-                const bool in = x0 >= 6 && x0 + tw + 6 <= nx && y0 >= 6 && y0 + th + 6 <= ny;
-                b->fused3.push_back(Tile{d, x0, y0, in ? 2 : 2 | 4});
+                const bool xin = x0 >= 6 && x0 + tw + 6 <= nx, yin = y0 >= 6 && y0 + th + 6 <= ny;
+                const bool xok = x0 + tw <= nx && (k[0] == LBM13_PERIODIC ? nx >= tw + 12 : xin);
+                const bool yok = y0 + th <= ny && (k[2] == LBM13_PERIODIC ? ny >= th + 12 : yin);
+                if (small && xok && yok) b->fused3.push_back(Tile{d, x0, y0, xin && yin ? 2 : 2 | 4});
+                else f3edge.push_back(Tile{d, x0, y0, 0});
             }
     }
-    if (!b->step3_ok) b->fused3.clear();
+    b->n3int = (int)b->fused3.size();
+    b->n3edge = (int)f3edge.size();
+    b->fused3.insert(b->fused3.end(), f3edge.begin(), f3edge.end());
+    if ((int)b->fused3.size() > b->L.tfmax) return fail(b, LBM13_EINVAL, "three-step tile table overflow");
     b->lines.clear();
     for (int d = 0; d < b->count; ++d) {
         const int* k = &b->sides_kind[4 * d];
@@ -521,11 +529,27 @@ hipError_t launch_two_steps(lbm13_batch* b, int from, hipStream_t s) {
     return e;
 }
 
+// Three time steps: interior tiles on stream s and the other tiles concurrently
+// on the auxiliary stream, as for two steps.
 template <typename R>
 hipError_t launch_three_steps(lbm13_batch* b, int from, hipStream_t s) {
     const Tile* tiles = reinterpret_cast<const Tile*>(b->ws + b->L.tiles_fused3);
-    return lbm13::launch_step3<R>(b->ftw, b->fth, buf<R>(b, from), buf<R>(b, 1 - from), doms_dev<R>(b), tiles,
-                                  (int)b->fused3.size(), s);
+    R* side = reinterpret_cast<R*>(b->ws + b->L.wall);
+    const R* src = buf<R>(b, from);
+    R* dst = buf<R>(b, 1 - from);
+    if (b->n3int == 0 || b->n3edge == 0 || !b->aux)
+        return lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->n3int, b->n3edge, side,
+                                      from, s);
+    hipError_t e = hipEventRecord(b->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->aux, b->ev_fork, 0);
+    if (e == hipSuccess)
+        e = lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles + b->n3int, 0, b->n3edge, side,
+                                   from, b->aux);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->aux);
+    if (e == hipSuccess)
+        e = lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->n3int, 0, side, from, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join, 0);
+    return e;
 }
 
 // Enqueue n steps as launches of spl steps (then 2 and 1 for the remainder),
@@ -594,8 +618,8 @@ int capture_graph(lbm13_batch* b, int parity) {
 template <typename R>
 int step_impl(lbm13_batch* b, long long n) {
     if (b->spl == 3 && !b->step3_ok)
-        return fail(b, LBM13_EINVAL, "three steps per launch need domains periodic on both axes, sides multiples "
-                                     "of a three-step tile shape and at least the tile + 12");
+        return fail(b, LBM13_EINVAL, "three steps per launch need a three-step tile shape (FP32: 64x16, 32x32, "
+                                     "64x8, 32x16; FP64: 64x8, 32x16, 32x8)");
     while (b->graph_k > 0 && n >= b->graph_k) {
         if (!b->gexec[b->cur]) {
             int st = capture_graph<R>(b, b->cur);
@@ -649,7 +673,7 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
     for (auto& f : kStep3Shapes[b->precision == LBM13_FP64 ? 0 : 1])
         if (f[0] > 0) cands.push_back(Cand{3, f[0], f[1], b->split});
     float best = 1e30f;
-    Cand pick{b->spl, b->spl == 2 ? b->ftw : b->tile_x, b->spl == 2 ? b->fth : b->tile_y, b->split};
+    Cand pick{b->spl, b->spl >= 2 ? b->ftw : b->tile_x, b->spl >= 2 ? b->fth : b->tile_y, b->split};
     int st = LBM13_OK;
     for (const Cand& c : cands) {
         b->spl = c.spl;
@@ -662,7 +686,7 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
             b->fth = c.h;
         }
         if ((st = rebuild(b))) break;
-        if (c.spl == 3 && !b->step3_ok) continue;  // not possible for these domains
+        if (c.spl == 3 && !b->step3_ok) continue;  // not a three-step shape
         if ((st = step_impl<R>(b, 6))) break;
         (void)hipEventRecord(e0, b->stream);
         if ((st = step_impl<R>(b, steps))) break;

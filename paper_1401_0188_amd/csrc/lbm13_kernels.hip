@@ -443,6 +443,36 @@ __device__ __forceinline__ void record_wall_layers(R* __restrict__ side, const D
     }
 }
 
+// A multi-step launch keeps, for the wall lines its region crosses, rho' and E'
+// (without the energy source) of the first wall layer and rho' of the second,
+// as its collided nodes give them: xs[2][RH][3] for the West and East walls by
+// region row, ys[2][RW][3] for the South and North walls by region column.
+template <typename R, int RW, int RH>
+__device__ __forceinline__ void record_region_layers(R* xs, R* ys, const Dom<R>& D, int X, int Y, int lx, int ly,
+                                                     const R g[13]) {
+    const bool xw = !D.xper && (X < 2 || X >= D.nx - 2);
+    const bool yw = !D.yper && (Y < 2 || Y >= D.ny - 2);
+    if (!xw && !yw) return;
+    R rho = R(0), E = -D.QE;
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+        rho += g[i];
+        E += R(c_M[1][i]) * g[i];
+    }
+    if (xw) {
+        if (X == 0) { xs[(0 * RH + ly) * 3 + 0] = rho; xs[(0 * RH + ly) * 3 + 1] = E; }
+        if (X == 1) xs[(0 * RH + ly) * 3 + 2] = rho;
+        if (X == D.nx - 1) { xs[(1 * RH + ly) * 3 + 0] = rho; xs[(1 * RH + ly) * 3 + 1] = E; }
+        if (X == D.nx - 2) xs[(1 * RH + ly) * 3 + 2] = rho;
+    }
+    if (yw) {
+        if (Y == 0) { ys[(0 * RW + lx) * 3 + 0] = rho; ys[(0 * RW + lx) * 3 + 1] = E; }
+        if (Y == 1) ys[(0 * RW + lx) * 3 + 2] = rho;
+        if (Y == D.ny - 1) { ys[(1 * RW + lx) * 3 + 0] = rho; ys[(1 * RW + lx) * 3 + 1] = E; }
+        if (Y == D.ny - 2) ys[(1 * RW + lx) * 3 + 2] = rho;
+    }
+}
+
 // XCD-aware block order: the hardware deals consecutive workgroups round-robin
 // to the 8 XCDs; this remap gives each XCD a contiguous run of tiles so the
 // shifted reads of neighbouring tiles hit the same L2.
@@ -650,28 +680,7 @@ void step2_kernel(const R* __restrict__ src, R* __restrict__ dst,
         if (D.collide) collide(g[k], D);
 #pragma unroll
         for (int i = 0; i < 13; ++i) lds[(i * RH + ly) * RW + lx] = g[k][i];
-        const bool xw = !D.xper && (X < 2 || X >= D.nx - 2);
-        const bool yw = !D.yper && (Y < 2 || Y >= D.ny - 2);
-        if (xw || yw) {
-            R rho = R(0), E = -D.QE;
-#pragma unroll
-            for (int i = 0; i < 13; ++i) {
-                rho += g[k][i];
-                E += R(c_M[1][i]) * g[k][i];
-            }
-            if (xw) {
-                if (X == 0) { xs[(0 * RH + ly) * 3 + 0] = rho; xs[(0 * RH + ly) * 3 + 1] = E; }
-                if (X == 1) xs[(0 * RH + ly) * 3 + 2] = rho;
-                if (X == D.nx - 1) { xs[(1 * RH + ly) * 3 + 0] = rho; xs[(1 * RH + ly) * 3 + 1] = E; }
-                if (X == D.nx - 2) xs[(1 * RH + ly) * 3 + 2] = rho;
-            }
-            if (yw) {
-                if (Y == 0) { ys[(0 * RW + lx) * 3 + 0] = rho; ys[(0 * RW + lx) * 3 + 1] = E; }
-                if (Y == 1) ys[(0 * RW + lx) * 3 + 2] = rho;
-                if (Y == D.ny - 1) { ys[(1 * RW + lx) * 3 + 0] = rho; ys[(1 * RW + lx) * 3 + 1] = E; }
-                if (Y == D.ny - 2) ys[(1 * RW + lx) * 3 + 2] = rho;
-            }
-        }
+        record_region_layers<R, RW, RH>(xs, ys, D, X, Y, lx, ly, g[k]);
     }
     __syncthreads();
 
@@ -906,6 +915,129 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
         if (D.collide) collide(q, D);
 #pragma unroll
         for (int i = 0; i < 13; ++i) buffer_store_nt<R>(q[i], out, c, (unsigned)(i * S * es));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Three steps per launch on the other tiles: tiles that reach a wall (their
+// region, a tile plus four nodes on each side, or its gathers), a ragged
+// domain edge or a periodic axis shorter than the region.  The state of each
+// level is kept over its whole region in LDS, as in step2_kernel: phase 1
+// advances the (TW + 8) x (TH + 8) region from HBM (wall fix-ups from the side
+// array of step t), phase 2 the (TW + 4) x (TH + 4) region from LDS into
+// registers (wall fix-ups from the layer values phase 1 kept), then, after a
+// barrier, stores it and its layer values over the first level; phase 3
+// advances the tile, writes HBM and the side array of step t + 3.  Region
+// nodes beyond a wall (or past a ragged edge) gather from a clamped node and
+// store nothing; no gather of an in-domain node reads them.  Each node's
+// arithmetic is the single-step kernel's.
+template <typename R, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu(
+    (13 * (TW + 8) * (TH + 8) + 6 * (TW + TH + 16)) * (int)sizeof(R), NT)))) void step3_wall_kernel(
+    const R* __restrict__ src, R* __restrict__ dst, const Dom<R>* __restrict__ doms, const Tile* __restrict__ tiles,
+    int ntiles, R* __restrict__ side, int from) {
+    constexpr int W1 = TW + 8, H1 = TH + 8, W2 = TW + 4, H2 = TH + 4;
+    constexpr int N1 = W1 * H1, N2 = W2 * H2, N3 = TW * TH;
+    constexpr int NI1 = (N1 + NT - 1) / NT, NI2 = (N2 + NT - 1) / NT;
+    __shared__ R lds[13 * N1];
+    __shared__ R xs[2 * H1 * 3];
+    __shared__ R ys[2 * W1 * 3];
+    const int t = xcd_tile(blockIdx.x, ntiles);
+    const Tile tl = tiles[t];
+    const Dom<R>& D = doms[tl.dom];
+    const R* __restrict__ a = src + D.off;
+    R* __restrict__ o = dst + D.off;
+    const int o1x = tl.x0 - 4, o1y = tl.y0 - 4, o2x = tl.x0 - 2, o2y = tl.y0 - 2;
+    const int tid = threadIdx.x;
+
+    // Phase 1: t -> t + 1 over the first level, gathers of all a thread's nodes
+    // issued before the first collision.
+    const GlobalSrc<R> G{a, D.plane, D.pitch, D.nx, D.ny, D.xper, D.yper};
+    const GlobalSide<R> GS{side, from};
+    const bool walls1 =
+        (!D.xper && (o1x < 2 || o1x + W1 > D.nx - 2)) || (!D.yper && (o1y < 2 || o1y + H1 > D.ny - 2));
+    R g[NI1][13];
+    int X1[NI1], Y1[NI1];
+    bool v1[NI1];
+#pragma unroll
+    for (int k = 0; k < NI1; ++k) {
+        const int r = min(tid + k * NT, N1 - 1);
+        int X = o1x + r % W1, Y = o1y + r / W1;
+        bool v = tid + k * NT < N1;
+        // a region wraps at most once around an axis at least as long as itself
+        if (D.xper) X = D.nx >= W1 ? wrap(X, D.nx) : pmod(X, D.nx);
+        else { v = v && X >= 0 && X < D.nx; X = min(max(X, 0), D.nx - 1); }
+        if (D.yper) Y = D.ny >= H1 ? wrap(Y, D.ny) : pmod(Y, D.ny);
+        else { v = v && Y >= 0 && Y < D.ny; Y = min(max(Y, 0), D.ny - 1); }
+        X1[k] = X;
+        Y1[k] = Y;
+        v1[k] = v;
+        if (walls1) gather_wall(G, GS, D, X, Y, g[k]);
+        else gather_bulk(a, D, X, Y, g[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NI1; ++k) {
+        if (!v1[k]) continue;
+        const int r = tid + k * NT, lx = r % W1, ly = r / W1;
+        if (D.collide) collide(g[k], D);
+#pragma unroll
+        for (int i = 0; i < 13; ++i) lds[(i * H1 + ly) * W1 + lx] = g[k][i];
+        record_region_layers<R, W1, H1>(xs, ys, D, X1[k], Y1[k], lx, ly, g[k]);
+    }
+    __syncthreads();
+
+    // Phase 2: t + 1 -> t + 2 over the second level, gathers from the first
+    // (coordinates unwrapped on periodic axes, as the region stores them).
+    const LdsSrc<R, W1, H1> L1{lds, o1x, o1y, D.nx, D.ny, D.xper, D.yper};
+    const LdsSide<R, W1, H1> S1{xs, ys, o1x, o1y};
+    const bool walls2 =
+        (!D.xper && (o2x < 2 || o2x + W2 > D.nx - 2)) || (!D.yper && (o2y < 2 || o2y + H2 > D.ny - 2));
+    R h[NI2][13];
+    bool v2[NI2];
+#pragma unroll
+    for (int k = 0; k < NI2; ++k) {
+        const int r = tid + k * NT;
+        const int lx = r % W2, ly = r / W2, X = o2x + lx, Y = o2y + ly;
+        v2[k] = r < N2 && (D.xper || (X >= 0 && X < D.nx)) && (D.yper || (Y >= 0 && Y < D.ny));
+        if (!v2[k]) continue;
+        if (walls2) {
+            gather_wall(L1, S1, D, X, Y, h[k]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 13; ++i) h[k][i] = lds[(i * H1 + ly + 2 - kVY[i]) * W1 + lx + 2 - kVX[i]];
+        }
+        if (D.collide) collide(h[k], D);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NI2; ++k) {
+        if (!v2[k]) continue;
+        const int r = tid + k * NT, lx = r % W2, ly = r / W2;
+#pragma unroll
+        for (int i = 0; i < 13; ++i) lds[(i * H2 + ly) * W2 + lx] = h[k][i];
+        record_region_layers<R, W2, H2>(xs, ys, D, o2x + lx, o2y + ly, lx, ly, h[k]);
+    }
+    __syncthreads();
+
+    // Phase 3: t + 2 -> t + 3 over the tile, gathers from the second level.
+    const LdsSrc<R, W2, H2> L2{lds, o2x, o2y, D.nx, D.ny, D.xper, D.yper};
+    const LdsSide<R, W2, H2> S2{xs, ys, o2x, o2y};
+    const bool walls3 = (!D.xper && (tl.x0 < 2 || tl.x0 + TW > D.nx - 2)) ||
+                        (!D.yper && (tl.y0 < 2 || tl.y0 + TH > D.ny - 2));
+    for (int r = tid; r < N3; r += NT) {
+        const int lx = r % TW + 2, ly = r / TW + 2;
+        const int X = o2x + lx, Y = o2y + ly;
+        if (X >= D.nx || Y >= D.ny) continue;
+        R q[13];
+        if (walls3) {
+            gather_wall(L2, S2, D, X, Y, q);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 13; ++i) q[i] = lds[(i * H2 + ly - kVY[i]) * W2 + lx - kVX[i]];
+        }
+        if (D.collide) collide(q, D);
+        store_node(o, D.plane, Y * D.pitch + X, q);
+        record_wall_layers(side, D, 1 - from, X, Y, q);
     }
 }
 
@@ -1419,16 +1551,20 @@ hipError_t launch_step2(int tw, int th, const R* src, R* dst, const Dom<R>* doms
     return hipErrorInvalidValue;
 }
 
-// Three steps per launch (domains periodic on both axes, whole tiles).
+// Three steps per launch: interior tiles tiles[0, nint) (flag 2, plus 4 where
+// the region wraps) on step3_kernel, the other tiles tiles[nint, nint + nedge)
+// on step3_wall_kernel.
 template <typename R>
-hipError_t launch_step3(int tw, int th, const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int ntiles,
-                        hipStream_t s) {
-    if (ntiles <= 0) return hipSuccess;
+hipError_t launch_step3(int tw, int th, const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int nint,
+                        int nedge, R* side, int from, hipStream_t s) {
 #define LBM13_STEP3(T, TW, TH)                                                                                 \
     if constexpr (std::is_same<R, T>::value) {                                                                 \
         if (tw == TW && th == TH) {                                                                            \
             constexpr int NT = sizeof(R) == 4 ? (TW * TH >= 1024 ? 1024 : 512) : (TW * TH >= 512 ? 512 : 256); \
-            step3_kernel<R, TW, TH, NT><<<ntiles, NT, 0, s>>>(src, dst, doms, tiles, ntiles);                 \
+            if (nint > 0) step3_kernel<R, TW, TH, NT><<<nint, NT, 0, s>>>(src, dst, doms, tiles, nint);       \
+            if (nedge > 0)                                                                                     \
+                step3_wall_kernel<R, TW, TH, NT>                                                               \
+                    <<<nedge, NT, 0, s>>>(src, dst, doms, tiles + nint, nedge, side, from);                    \
             return hipGetLastError();                                                                          \
         }                                                                                                      \
     }
@@ -1486,7 +1622,8 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
                                        R*, int, hipStream_t);                                                     \
     template hipError_t launch_step2<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int,     \
                                         hipStream_t);                                                             \
-    template hipError_t launch_step3<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, hipStream_t);   \
+    template hipError_t launch_step3<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int,     \
+                                        hipStream_t);                                                             \
     template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, int,          \
                                             hipStream_t);                                                         \
     template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, R*,     \

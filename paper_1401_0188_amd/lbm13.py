@@ -30,7 +30,7 @@ FOURIER_FIELDS = ("rho", "ux", "uy", "E")
 TILE_SHAPES = ((64, 4), (64, 8), (64, 16), (32, 8), (32, 16))
 _FUSED = ((64, 16), (64, 12), (64, 8), (64, 4), (32, 32), (32, 16), (32, 8), (32, 4))
 FUSED_TILE_SHAPES = {FP32_DEV: _FUSED, FP64: _FUSED}
-# tiles of three steps per launch (domains periodic on both axes)
+# tiles of three steps per launch
 STEP3_TILE_SHAPES = {FP32_DEV: ((64, 16), (32, 32), (64, 8), (32, 16)), FP64: ((64, 8), (32, 16), (32, 8))}
 
 

@@ -783,44 +783,132 @@ def test_three_steps_per_launch_matches_single_steps(precision):
     rng = np.random.default_rng(11)
     fields = (1 + 0.01 * rng.standard_normal((ny, nx)), 0.01 * rng.standard_normal((ny, nx)),
               0.01 * rng.standard_normal((ny, nx)), -2 + 0.01 * rng.standard_normal((ny, nx)))
-    for collide in (0, 1):
-        states = []
-        for spl in (1, 3):
-            say("three-step vs single-step precision %d, collide %d, spl %d" % (precision, collide, spl))
-            lat = lbm13.Lattice(nx, ny, precision)
-            lat.set_fused_tile(*lbm13.STEP3_TILE_SHAPES[precision][0])
-            lat.set_steps_per_launch(spl)
-            lat.set_params(g=(1e-4, -1e-4), collide=collide)
-            lat.init_moments(*fields)
-            lat.step(30)
-            states.append(lat.get_state().cpu().numpy())
-            lat.destroy()
-        if collide == 0:
-            assert np.array_equal(states[0], states[1])
-        else:
-            err = np.abs(states[0] - states[1]).max() / np.abs(states[0]).max()
-            assert err <= (1e-14 if precision == 0 else 1e-6), err
+    for kinds in ((0, 0, 0, 0), (2, 2, 1, 1)):
+        sides = lbm13.make_sides(kinds, (0.0, 0.0, 0.01, 0.0), (-1.99, -2.01, 0, 0))
+        for collide in (0, 1):
+            states = []
+            for spl in (1, 3):
+                say("three-step vs single-step precision %d, sides %s, collide %d, spl %d" %
+                    (precision, kinds, collide, spl))
+                lat = lbm13.Lattice(nx, ny, precision)
+                lat.set_fused_tile(*lbm13.STEP3_TILE_SHAPES[precision][0])
+                lat.set_steps_per_launch(spl)
+                lat.set_params(sides=sides, g=(1e-4, -1e-4), collide=collide)
+                lat.init_moments(*fields)
+                lat.step(30)
+                states.append(lat.get_state().cpu().numpy())
+                lat.destroy()
+            if collide == 0:
+                assert np.array_equal(states[0], states[1])
+            else:
+                err = np.abs(states[0] - states[1]).max() / np.abs(states[0]).max()
+                assert err <= (1e-14 if precision == 0 else 1e-6), err
 
 
-def test_three_steps_per_launch_rejects_walls_and_ragged_sides():
+def test_three_steps_per_launch_rejects_other_tile_shapes():
     lbm13 = _lb()
-    say("three-step feasibility errors")
+    say("three-step tile shape error")
     lat = lbm13.Lattice(128, 96, lbm13.FP32_DEV)
-    lat.set_fused_tile(64, 16)
+    lat.set_fused_tile(64, 12)  # a two-step shape only
     lat.set_steps_per_launch(3)
-    lat.set_params(sides=lbm13.make_sides((2, 2, 0, 0), (0, 0, 0, 0), (-1.99, -2.01, 0, 0)))
+    lat.set_params()
     lat.init_moments(*workloads.rest_fields(128, 96))
     with pytest.raises(lbm13.LBM13Error):
         lat.step(3)
     lat.destroy()
-    lat = lbm13.Lattice(130, 96, lbm13.FP32_DEV)  # 130 is not a multiple of 64
-    lat.set_fused_tile(64, 16)
-    lat.set_steps_per_launch(3)
-    lat.set_params()
-    lat.init_moments(*workloads.rest_fields(130, 96))
-    with pytest.raises(lbm13.LBM13Error):
-        lat.step(3)
+
+
+@pytest.mark.parametrize("name", sorted(WALL_CASES))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_three_steps_per_launch_walls(name, precision):
+    """Three time steps per launch with walls (the wall states of the two
+    intermediate steps come from the levels kept in LDS) against the oracle,
+    with a remainder done by shorter launches."""
+    nx, ny, kinds, u_t, T_w, extra, steps = WALL_CASES[name]
+    steps = steps + 2
+    say("three-step %s precision %d, %d steps" % (name, precision, steps))
+    fields = workloads.cavity_fields(nx, ny=ny, seed=19, dT=0.01)
+    lat, gs, gm, fs, om, *_ = run_both(nx, ny, fields, steps, kinds, u_t, T_w, precision=precision, spl=3, **extra)
+    assert lat.launch_config()["steps_per_launch"] == 3
+    if precision == 0:
+        assert_fp64(gs, gm, fs, om)
+    else:
+        assert_fp32(gm, om)
     lat.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_three_step_tile_shape(precision):
+    """Every three-step tile shape on a closed moving-wall cavity (no interior
+    tile), a 203 x 93 domain with walls on y (interior tiles run concurrently
+    with the wall kernel), the same domain fully periodic with ragged edges, and
+    a periodic 37 x 24 domain shorter than the region (regions wrap more than
+    once), with graph replay."""
+    lbm13 = _lb()
+    nx, ny, kinds, u_t, T_w, extra, steps = WALL_CASES["closed_moving_adiabatic"]
+    cases = [(nx, ny, workloads.cavity_fields(nx, ny=ny, seed=31), kinds, u_t, T_w, extra),
+             (203, 93, workloads.shear_acoustic(203, 93), (0, 0, 2, 1), (0, 0, 0.02, -0.01),
+              (0, 0, -1.99, 0), dict(g=(0.0, -1e-4))),
+             (203, 93, workloads.shear_acoustic(203, 93), (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0),
+              dict(F0=(1e-5, -2e-5))),
+             (37, 24, workloads.shear_acoustic(37, 24), (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0),
+              dict(g=(1e-3, 0.0)))]
+    for ft in lbm13.STEP3_TILE_SHAPES[precision]:
+        for cnx, cny, fields, ck, cu, cT, cx in cases:
+            say("three-step tile %s precision %d, %d x %d sides %s" % (ft, precision, cnx, cny, ck))
+            lat, gs, gm, fs, om, *_ = run_both(cnx, cny, fields, 31, ck, cu, cT, precision=precision, spl=3,
+                                               fused_tile=ft, graph=12, **cx)
+            if precision == 0:
+                assert_fp64(gs, gm, fs, om)
+            else:
+                assert_fp32(gm, om)
+            lat.destroy()
+
+
+def test_three_steps_per_launch_streaming_is_bit_exact():
+    """Collisions off, walls at rest and adiabatic (every wall term is zero, so
+    no arithmetic is left): three-step launches are exactly the oracle's
+    streaming and path reversals, through both kernels, ragged tiles and
+    periodic wraps.  Moving and temperature walls, whose wall terms are
+    computed in the working precision, are covered against the oracle to the
+    parity bounds by the three-step wall tests."""
+    lbm13 = _lb()
+    rng = np.random.default_rng(5)
+    for nx, ny in ((70, 35), (203, 93)):
+        fields = (1 + 0.01 * rng.standard_normal((ny, nx)), 0.01 * rng.standard_normal((ny, nx)),
+                  0.01 * rng.standard_normal((ny, nx)), -2 + 0.01 * rng.standard_normal((ny, nx)))
+        for kinds in ((1, 1, 1, 1), (0, 0, 1, 1), (1, 1, 0, 0), (0, 0, 0, 0)):
+            say("three-step collide-off %d x %d sides %s" % (nx, ny, kinds))
+            lat = lbm13.Lattice(nx, ny, lbm13.FP32_DEV)
+            lat.set_fused_tile(32, 16)
+            lat.set_params(sides=lbm13.make_sides(kinds), collide=0)
+            lat.set_steps_per_launch(3)
+            lat.init_moments(*fields)
+            s0 = lat.get_state().cpu().numpy()
+            lat.step(24)
+            ref = oracle.run(s0, oracle.params(collide=0), oracle.sides(kinds), 24)
+            assert np.array_equal(lat.get_state().cpu().numpy(), ref)
+            lat.destroy()
+
+
+@pytest.mark.parametrize("workload", ["cavities64", "channels128"])
+def test_three_steps_per_launch_batched_full_size(workload):
+    lbm13 = _lb()
+    import bench
+    specs = bench.cavity_specs() if workload == "cavities64" else bench.channel_specs()
+    steps = 201
+    say("three-step %s full batch, %d steps" % (workload, steps))
+    b = bench.build_batch(specs, lbm13.FP32_DEV)
+    b.set_fused_tile(32, 16)
+    b.set_steps_per_launch(3)
+    b.use_graph(48)
+    b.step(steps)
+    assert all(d["nonfinite"] == 0 for d in b.diagnostics())
+    order = sorted(range(len(specs)), key=lambda i: specs[i]["nx"] * specs[i]["ny"])[:3]
+    for i in order:
+        om = _oracle_for_spec(specs[i], steps)
+        gm = [t.cpu().numpy() for t in b.moments(i)]
+        assert_fp32(gm, om)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
