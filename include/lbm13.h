@@ -219,7 +219,7 @@ int lbm13_use_graph(lbm13_ctx *ctx, int k);
  * LDS; tiles far from walls and ragged edges run a kernel that keeps only the
  * windows the next level reads, the others keep each level's whole region;
  * the two-step tile must be a three-step shape: FP32 (64, 16), (32, 32),
- * (64, 8), (32, 16); FP64 (64, 8), (32, 16), (32, 8); lbm13_step returns
+ * (64, 8), (32, 16), (32, 8); FP64 (64, 8), (32, 16), (32, 8); lbm13_step returns
  * EINVAL otherwise).  A remainder of lbm13_step(n) is done by shorter
  * launches.  EINVAL for other values. */
 int lbm13_set_steps_per_launch(lbm13_ctx *ctx, int k);

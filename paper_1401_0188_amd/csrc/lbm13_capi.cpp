@@ -62,7 +62,8 @@ const int kShapes[][2] = {{64, 4}, {64, 8}, {64, 16}, {32, 8}, {32, 16}};
 const int kFusedShapes[][2] = {{64, 16}, {64, 12}, {64, 8}, {64, 4}, {32, 32}, {32, 16}, {32, 8}, {32, 4}};
 
 // three steps per launch: compiled tile shapes per precision (FP64 first)
-const int kStep3Shapes[2][4][2] = {{{64, 8}, {32, 16}, {32, 8}, {0, 0}}, {{64, 16}, {32, 32}, {64, 8}, {32, 16}}};
+const int kStep3Shapes[2][5][2] = {{{64, 8}, {32, 16}, {32, 8}, {0, 0}, {0, 0}},
+                                   {{64, 16}, {32, 32}, {64, 8}, {32, 16}, {32, 8}}};
 
 bool step3_shape(int precision, int tw, int th) {
     for (auto& f : kStep3Shapes[precision == LBM13_FP64 ? 0 : 1])
@@ -619,7 +620,7 @@ template <typename R>
 int step_impl(lbm13_batch* b, long long n) {
     if (b->spl == 3 && !b->step3_ok)
         return fail(b, LBM13_EINVAL, "three steps per launch need a three-step tile shape (FP32: 64x16, 32x32, "
-                                     "64x8, 32x16; FP64: 64x8, 32x16, 32x8)");
+                                     "64x8, 32x16, 32x8; FP64: 64x8, 32x16, 32x8)");
     while (b->graph_k > 0 && n >= b->graph_k) {
         if (!b->gexec[b->cur]) {
             int st = capture_graph<R>(b, b->cur);

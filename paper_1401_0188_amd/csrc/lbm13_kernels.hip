@@ -1560,7 +1560,7 @@ hipError_t launch_step3(int tw, int th, const R* src, R* dst, const Dom<R>* doms
 #define LBM13_STEP3(T, TW, TH)                                                                                 \
     if constexpr (std::is_same<R, T>::value) {                                                                 \
         if (tw == TW && th == TH) {                                                                            \
-            constexpr int NT = sizeof(R) == 4 ? (TW * TH >= 1024 ? 1024 : 512) : (TW * TH >= 512 ? 512 : 256); \
+            constexpr int NT = sizeof(R) == 4 ? (TW * TH < 256 ? 256 : TW * TH) : (TW * TH >= 512 ? 512 : 256); \
             if (nint > 0) step3_kernel<R, TW, TH, NT><<<nint, NT, 0, s>>>(src, dst, doms, tiles, nint);       \
             if (nedge > 0)                                                                                     \
                 step3_wall_kernel<R, TW, TH, NT>                                                               \
@@ -1572,6 +1572,7 @@ hipError_t launch_step3(int tw, int th, const R* src, R* dst, const Dom<R>* doms
     LBM13_STEP3(float, 32, 32)
     LBM13_STEP3(float, 64, 8)
     LBM13_STEP3(float, 32, 16)
+    LBM13_STEP3(float, 32, 8)
     LBM13_STEP3(double, 64, 8)
     LBM13_STEP3(double, 32, 16)
     LBM13_STEP3(double, 32, 8)

@@ -31,7 +31,7 @@ TILE_SHAPES = ((64, 4), (64, 8), (64, 16), (32, 8), (32, 16))
 _FUSED = ((64, 16), (64, 12), (64, 8), (64, 4), (32, 32), (32, 16), (32, 8), (32, 4))
 FUSED_TILE_SHAPES = {FP32_DEV: _FUSED, FP64: _FUSED}
 # tiles of three steps per launch
-STEP3_TILE_SHAPES = {FP32_DEV: ((64, 16), (32, 32), (64, 8), (32, 16)), FP64: ((64, 8), (32, 16), (32, 8))}
+STEP3_TILE_SHAPES = {FP32_DEV: ((64, 16), (32, 32), (64, 8), (32, 16), (32, 8)), FP64: ((64, 8), (32, 16), (32, 8))}
 
 
 class LBM13Error(RuntimeError):
