@@ -53,7 +53,7 @@ def launch_kernels(launch):
         return (1, tuple(launch["tile"]))
     if spl == 2:
         return (2, tuple(launch["fused_tile"]), bool(launch["interior_kernel"]))
-    return (3, tuple(launch["fused_tile"]))
+    return (3, tuple(launch["fused_tile"]), bool(launch["interior_kernel"]))
 
 
 def measured_traffic(key, launch):

@@ -232,11 +232,14 @@ int lbm13_set_steps_per_launch(lbm13_ctx *ctx, int k);
  * Defaults: (32, 32) FP32, (32, 16) FP64.  EINVAL otherwise. */
 int lbm13_set_fused_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
 
-/* Two-step launches: 1 (default) runs the tiles whose region lies inside the
- * domain away from walls and wraps on a separate kernel that keeps 13 x tile
- * values in LDS, concurrently with the general kernel on the other tiles;
- * 0 runs every tile on the general kernel (fewer, better balanced workgroups
- * for batches of small domains).  Results are identical.  EINVAL otherwise. */
+/* Two- and three-step launches: 1 (default) runs the tiles whose region lies
+ * inside the domain away from walls (and, for two steps, wraps) on a separate
+ * kernel that keeps only the windows the next level reads in LDS,
+ * concurrently with the general kernel on the other tiles; 0 runs every tile
+ * on the general kernel (fewer, better balanced workgroups for batches of
+ * small domains).  Two steps: identical results; three steps: identical with
+ * collisions off, equal to rounding with them on (the two kernels contract
+ * the same arithmetic differently).  EINVAL otherwise. */
 int lbm13_set_interior_kernel(lbm13_ctx *ctx, int on);
 
 /* Destroy the context (frees host objects and graphs; never the workspace). */

@@ -334,7 +334,8 @@ int rebuild(lbm13_batch* b) {
     // tile) stay at least two nodes from every wall, on a periodic axis a side
     // of at least the tile + 12 (the region and its reach wrap at most once),
     // planes within 32-bit byte offsets; flag 2, plus 4 where the region wraps.
-    // The other tiles run step3_wall_kernel.
+    // The other tiles, and every tile with the interior kernel off, run
+    // step3_wall_kernel.
     b->fused3.clear();
     b->step3_ok = step3_shape(b->precision, b->ftw, b->fth);
     std::vector<Tile> f3edge;
@@ -347,7 +348,7 @@ int rebuild(lbm13_batch* b) {
                 const bool xin = x0 >= 6 && x0 + tw + 6 <= nx, yin = y0 >= 6 && y0 + th + 6 <= ny;
                 const bool xok = x0 + tw <= nx && (k[0] == LBM13_PERIODIC ? nx >= tw + 12 : xin);
                 const bool yok = y0 + th <= ny && (k[2] == LBM13_PERIODIC ? ny >= th + 12 : yin);
-                if (small && xok && yok) b->fused3.push_back(Tile{d, x0, y0, xin && yin ? 2 : 2 | 4});
+                if (b->split && small && xok && yok) b->fused3.push_back(Tile{d, x0, y0, xin && yin ? 2 : 2 | 4});
                 else f3edge.push_back(Tile{d, x0, y0, 0});
             }
     }
@@ -672,7 +673,8 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
         if (fused_fits(b->precision, f[0], f[1]))
             for (int sp = 1; sp >= 0; --sp) cands.push_back(Cand{2, f[0], f[1], sp});
     for (auto& f : kStep3Shapes[b->precision == LBM13_FP64 ? 0 : 1])
-        if (f[0] > 0) cands.push_back(Cand{3, f[0], f[1], b->split});
+        if (f[0] > 0)
+            for (int sp = 1; sp >= 0; --sp) cands.push_back(Cand{3, f[0], f[1], sp});
     float best = 1e30f;
     Cand pick{b->spl, b->spl >= 2 ? b->ftw : b->tile_x, b->spl >= 2 ? b->fth : b->tile_y, b->split};
     int st = LBM13_OK;

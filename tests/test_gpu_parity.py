@@ -248,7 +248,8 @@ def launch_candidates(lbm13, precision):
         for on in (True, False):
             out.append(dict(spl=2, fused_tile=ft, interior_kernel=on))
     for ft in lbm13.STEP3_TILE_SHAPES[precision]:
-        out.append(dict(spl=3, fused_tile=ft, interior_kernel=True))
+        for on in (True, False):
+            out.append(dict(spl=3, fused_tile=ft, interior_kernel=on))
     return out
 
 
@@ -932,6 +933,36 @@ def test_interior_kernel_switch_is_bit_exact(precision):
         states.append(lat.get_state().cpu().numpy())
         lat.destroy()
     assert np.array_equal(states[0], states[1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_three_step_interior_kernel_switch(precision):
+    """Three-step launches with the interior tiles on the window kernel (run
+    concurrently with the general kernel) and with every tile on the general
+    kernel: identical bits with collisions off, equal to rounding with them
+    on, on a domain with walls on y, ragged edges and interior tiles."""
+    lbm13 = _lb()
+    fields = workloads.shear_acoustic(203, 93)
+    sides = lbm13.make_sides((0, 0, 2, 1), (0, 0, 0.02, -0.01), (0, 0, -1.99, 0))
+    for collide in (0, 1):
+        states = []
+        for on in (True, False):
+            say("three-step interior kernel %s precision %d collide %d" % (on, precision, collide))
+            lat = lbm13.Lattice(203, 93, precision)
+            lat.set_fused_tile(32, 16)
+            lat.set_steps_per_launch(3)
+            lat.set_interior_kernel(on)
+            assert lat.launch_config()["interior_kernel"] == on
+            lat.set_params(sides=sides, g=(0.0, -1e-4), collide=collide)
+            lat.init_moments(*fields)
+            lat.step(24)
+            states.append(lat.get_state().cpu().numpy())
+            lat.destroy()
+        if collide == 0:
+            assert np.array_equal(states[0], states[1])
+        else:
+            err = np.abs(states[0] - states[1]).max() / np.abs(states[0]).max()
+            assert err <= (1e-14 if precision == 0 else 1e-6), err
 
 
 def test_autotune_considers_two_step_launches():
