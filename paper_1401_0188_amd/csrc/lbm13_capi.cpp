@@ -423,12 +423,6 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
     D->collide = p->collide ? 1 : 0;
     const double a1 = p->c1 + dv->h1 + dv->k1 * p->E0;
     const double a2 = dv->c2 + dv->h2 + p->k2 * p->E0;
-    D->s_eps = R(p->s_eps);
-    D->s_vp = R(p->s_varpi);
-    D->s_q = R(dv->s_q);
-    D->s_r = R(p->s_rx);
-    D->s_XX = R(p->s_XX);
-    D->s_XXe = R(p->s_XXe);
     D->c_er = R(dv->c_eps_rho);
     D->c_eE = R(p->c_epsE);
     D->c_vr = R(p->c_varpi_rho);
@@ -440,10 +434,6 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
     D->h2 = R(dv->h2);
     D->k2 = R(p->k2);
     const double F0x = p->F0[0] + p->g[0] * (1.0 - p->rho0), F0y = p->F0[1] + p->g[1] * (1.0 - p->rho0);
-    D->F0x = R(F0x);
-    D->F0y = R(F0y);
-    D->gx = R(p->g[0]);
-    D->gy = R(p->g[1]);
     D->F0x_d = F0x;
     D->F0y_d = F0y;
     D->gx_d = p->g[0];

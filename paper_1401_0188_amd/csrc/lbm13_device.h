@@ -27,15 +27,11 @@ struct alignas(16) Dom {
     int tile0, ntiles;  // range of this domain in the domain-ordered tile table
     int collide;
     int pad0;
-    // relaxation rates of eps, varpi, q (x and y), r (x and y), XX (and XY), XXe
-    R s_eps, s_vp, s_q, s_r, s_XX, s_XXe;
     // equilibria about rest: eps' = c_er rho' + c_eE E', varpi' = c_vr rho' + c_vE E',
     // q = j (a1 + h1 rho' + k1 E'), r = j (a2 + h2 rho' + k2 E'),  (rho', E' deviations)
     R c_er, c_eE, c_vr, c_vE;
     R a1, h1, k1, a2, h2, k2;
-    // body force F = F0 + g rho' (F0 already holds F0 + g (1 - rho0)); energy source
-    R F0x, F0y, gx, gy;
-    R QE;  // Q_E: the kept post-collision state carries E(t) + Q_E
+    R QE;  // Q_E, the energy source: the kept post-collision state carries E(t) + Q_E
     // relaxation folded with the norms D_k for the collision:
     //   s_eps (eps - eps^eq) / 42196 = sum_j aeps[j] (g0, S1, S2, S3)_j and
     //   s_varpi (varpi - varpi^eq) / 548 = sum_j avp[j] (g0, S1, S2, S3)_j, with
@@ -43,7 +39,7 @@ struct alignas(16) Dom {
     //   the populations); eQ[c] = -M_E,c Q_E / 4004, the energy source as
     //   Delta_E = -Q_E for the rest population and the three classes;
     //   kX = s_XX / 68, kY = s_XX / 4, kXe = s_XXe / 68, kq = s_q / 20, kr = s_r / 70,
-    //   -F / 14 = fjx + gjx rho' (and y)
+    //   -F / 14 = fjx + gjx rho' (and y) for the body force F = F0 + g (rho - rho0)
     R aeps[4], avp[4];
     R eQ[4];
     R kX, kY, kXe, kq, kr;
@@ -54,7 +50,7 @@ struct alignas(16) Dom {
     // FP64 constants
     double E0;
     double frest[4];  // rest populations of the |v|^2 = 0, 1, 2, 4 classes
-    double F0x_d, F0y_d, gx_d, gy_d;
+    double F0x_d, F0y_d, gx_d, gy_d;  // F = (F0x_d, F0y_d) + (gx_d, gy_d) rho
     double B;         // equilibrium E flux per unit momentum
     double QE_d;      // Q_E in FP64
     double nu_scale;  // nx / (kappa_E (T_W - T_E)), 0 when T_W == T_E

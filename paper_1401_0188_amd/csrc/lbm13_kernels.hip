@@ -11,7 +11,9 @@
 // coalesced non-temporal stores.  One wavefront covers 64 (or 2 x 32)
 // consecutive nodes of a row, so every population plane is read and written
 // as contiguous 256/512-byte segments; the +-1/+-2 shifted reads of
-// neighbouring wavefronts share cache lines in L2.
+// neighbouring wavefronts share cache lines in L2.  The two- and three-step
+// kernels advance a tile and a halo of two nodes per extra step, keeping the
+// intermediate states in LDS, so HBM is read and written once per launch.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -26,7 +28,6 @@ namespace lbm13 {
 // the bulk collision below uses the same matrix in pair-symmetric form.
 __constant__ int c_vx[13] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0};
 __constant__ int c_vy[13] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2};
-__constant__ int c_opp[13] = {0, 3, 4, 1, 2, 7, 8, 5, 6, 11, 12, 9, 10};
 __constant__ int c_cls[13] = {0, 1, 1, 1, 1, 2, 2, 2, 2, 3, 3, 3, 3};  // |v|^2 class
 __constant__ float c_M[13][13] = {
     {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
@@ -43,8 +44,6 @@ __constant__ float c_M[13][13] = {
     {0, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0},
     {0, -4, 4, -4, 4, 0, 0, 0, 0, 1, -1, 1, -1}};
 __constant__ float c_D[13] = {13, 4004, 42196, 548, 14, 14, 20, 20, 70, 70, 68, 4, 68};
-__constant__ double c_invD[13] = {1.0 / 13, 1.0 / 4004, 1.0 / 42196, 1.0 / 548, 1.0 / 14, 1.0 / 14, 1.0 / 20,
-                                  1.0 / 20, 1.0 / 70, 1.0 / 70, 1.0 / 68, 1.0 / 4, 1.0 / 68};
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -179,13 +178,6 @@ __device__ __forceinline__ void node_rho_E(const R* __restrict__ b, const Dom<R>
     }
     rho = r;
     E = e;
-}
-
-// Whether link i crossing wall w is an anti-bounce-back link: normal to a
-// temperature wall (sec. 7: links with a tangential component bounce back).
-__device__ __forceinline__ bool abb_link(int kind, int w, int i) {
-    const bool normal = (w < 2) ? (c_vy[i] == 0) : (c_vx[i] == 0);
-    return normal && kind == kDirichletT;
 }
 
 // Side array of the wall layers: for every position along every wall, rho' and
