@@ -34,7 +34,10 @@ BYTES_PER_LU = {0: 208, 1: 104}  # 13 loads + 13 stores of populations, FP64 / F
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E
 METRIC = "MLUPS and % of HBM roofline, FP32/batched vs plain FP64 GPU at stated error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1401_0188_amd", "csrc", "lbm13_kernels.hip")
+# the sources that decide what the timed kernels do: the kernels, the descriptor
+# layout and the host code that builds the tile tables and launches
+KERNEL_SRC = [os.path.join(ROOT, "paper_1401_0188_amd", "csrc", f)
+              for f in ("lbm13_kernels.hip", "lbm13_device.h", "lbm13_capi.cpp")]
 
 
 def log(msg):
@@ -42,8 +45,11 @@ def log(msg):
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def launch_kernels(launch):

@@ -65,6 +65,11 @@ const int kFusedShapes[][2] = {{64, 16}, {64, 12}, {64, 8}, {64, 4}, {32, 32}, {
 const int kStep3Shapes[2][5][2] = {{{64, 8}, {32, 16}, {32, 8}, {0, 0}, {0, 0}},
                                    {{64, 16}, {32, 32}, {64, 8}, {32, 16}, {32, 8}}};
 
+// Width, in tiles, of the column bands the three-step tile table is ordered in
+// (measured on the 4096^2 wave: 16 for every FP32 tile against 4, 8 and 32;
+// 32 for FP64 against 8 and 16).
+constexpr int kBandTiles[2] = {32, 16};  // FP64, FP32
+
 bool step3_shape(int precision, int tw, int th) {
     for (auto& f : kStep3Shapes[precision == LBM13_FP64 ? 0 : 1])
         if (f[0] == tw && f[1] == th) return true;
@@ -343,14 +348,21 @@ int rebuild(lbm13_batch* b) {
         const int* k = &b->sides_kind[4 * d];
         const int nx = b->nx[d], ny = b->ny[d], tw = b->ftw, th = b->fth;
         const bool small = (13LL * b->L.plane[d] + 2LL * b->L.pitch[d] + 2) * es <= (long long)INT32_MAX;
-        for (int y0 = 0; y0 < ny; y0 += th)
-            for (int x0 = 0; x0 < nx; x0 += tw) {
-                const bool xin = x0 >= 6 && x0 + tw + 6 <= nx, yin = y0 >= 6 && y0 + th + 6 <= ny;
-                const bool xok = x0 + tw <= nx && (k[0] == LBM13_PERIODIC ? nx >= tw + 12 : xin);
-                const bool yok = y0 + th <= ny && (k[2] == LBM13_PERIODIC ? ny >= th + 12 : yin);
-                if (b->split && small && xok && yok) b->fused3.push_back(Tile{d, x0, y0, xin && yin ? 2 : 2 | 4});
-                else f3edge.push_back(Tile{d, x0, y0, 0});
-            }
+        // column bands of kBandTiles tiles: the XCDs take contiguous runs of the
+        // table, so a run covers few columns and many rows, and the halo rows a
+        // tile shares with the tiles above and below are read while still in L2
+        const int bw = tw * kBandTiles[b->precision == LBM13_FP64 ? 0 : 1];
+        for (int bx = 0; bx < nx; bx += bw)
+            for (int y0 = 0; y0 < ny; y0 += th)
+                for (int x0 = bx; x0 < std::min(nx, bx + bw); x0 += tw) {
+                    const bool xin = x0 >= 6 && x0 + tw + 6 <= nx, yin = y0 >= 6 && y0 + th + 6 <= ny;
+                    const bool xok = x0 + tw <= nx && (k[0] == LBM13_PERIODIC ? nx >= tw + 12 : xin);
+                    const bool yok = y0 + th <= ny && (k[2] == LBM13_PERIODIC ? ny >= th + 12 : yin);
+                    if (b->split && small && xok && yok)
+                        b->fused3.push_back(Tile{d, x0, y0, xin && yin ? 2 : 2 | 4});
+                    else
+                        f3edge.push_back(Tile{d, x0, y0, 0});
+                }
     }
     b->n3int = (int)b->fused3.size();
     b->n3edge = (int)f3edge.size();
