@@ -891,16 +891,20 @@ def test_three_steps_per_launch_streaming_is_bit_exact():
             lat.destroy()
 
 
+@pytest.mark.parametrize("interior", [True, False])
 @pytest.mark.parametrize("workload", ["cavities64", "channels128"])
-def test_three_steps_per_launch_batched_full_size(workload):
+def test_three_steps_per_launch_batched_full_size(workload, interior):
+    """The full batches in the benchmark's three-step configurations (interior
+    tiles on the window kernel or every tile on the general kernel)."""
     lbm13 = _lb()
     import bench
     specs = bench.cavity_specs() if workload == "cavities64" else bench.channel_specs()
     steps = 201
-    say("three-step %s full batch, %d steps" % (workload, steps))
+    say("three-step %s full batch, interior kernel %s, %d steps" % (workload, interior, steps))
     b = bench.build_batch(specs, lbm13.FP32_DEV)
     b.set_fused_tile(32, 16)
     b.set_steps_per_launch(3)
+    b.set_interior_kernel(interior)
     b.use_graph(48)
     b.step(steps)
     assert all(d["nonfinite"] == 0 for d in b.diagnostics())
