@@ -202,7 +202,8 @@ int lbm13_set_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
 int lbm13_autotune(lbm13_ctx *ctx, int steps, int *tile_x, int *tile_y);
 
 /* Current launch configuration: cfg = {steps per launch, single-step tile_x,
- * tile_y, two-step tile_x, tile_y, interior kernel on (1) or off (0)}.
+ * tile_y, two- and three-step tile_x, tile_y, interior kernel on (1) or off
+ * (0)}.
  * Host-only. */
 int lbm13_launch_config(const lbm13_ctx *ctx, int cfg[6]);
 
@@ -224,8 +225,9 @@ int lbm13_use_graph(lbm13_ctx *ctx, int k);
  * launches.  EINVAL for other values. */
 int lbm13_set_steps_per_launch(lbm13_ctx *ctx, int k);
 
-/* Tile of the two-steps-per-launch kernels: (64, 16), (64, 12), (64, 8),
- * (64, 4), (32, 32), (32, 16), (32, 8) or (32, 4) nodes, both precisions.
+/* Tile of the two- and three-steps-per-launch kernels: (64, 16), (64, 12),
+ * (64, 8), (64, 4), (32, 32), (32, 16), (32, 8) or (32, 4) nodes, both
+ * precisions (three steps take the subset listed above).
  * Tiles whose region (tile + 2-node halo) and its sources lie inside the domain
  * away from walls and wraps run a kernel that keeps only 13 x tile values in
  * LDS; the others keep the region (up to 141 KB, FP64 64 x 16).
