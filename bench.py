@@ -317,8 +317,10 @@ def roofline(nodes, kernel_ms, precision, traffic=None, spl=1):
         out["traffic_GBps"] = round(traffic / (kernel_ms * 1e-3) / 1e9, 1)
     if spl > 1:
         out["note"] = ("%d steps per launch: the algorithmic bytes are those of %d single steps, the HBM bytes "
-                       "moved are `traffic` (rocprofv3 counters); the three-step kernels are bound by vector ALU "
-                       "issue (FP32) or latency (FP64), profiles/step3_kernel_4096_counters.md" % (spl, spl))
+                       "moved are `traffic` (rocprofv3 counters)" % (spl, spl))
+        if spl == 3:
+            out["note"] += ("; on the wave the three-step kernel is bound by vector ALU issue (FP32) or latency "
+                            "(FP64), profiles/step3_kernel_4096_counters.md")
     return out
 
 
