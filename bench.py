@@ -30,6 +30,7 @@ BENCH_CONFIG = {1: dict(spl=2, fused_tile=(32, 32), tile=(64, 8)),
                 0: dict(spl=2, fused_tile=(32, 16), tile=(64, 8))}
 BENCH_TILE = BENCH_CONFIG[1]["tile"]
 GRAPH_K = 120                 # steps per captured HIP graph (a multiple of 2 and 3: whole multi-step launches)
+ACCURACY_STEPS = 10000        # FP32 against FP64 on the GPU after this many steps (the stated FP32 bound's horizon)
 BYTES_PER_LU = {0: 208, 1: 104}  # 13 loads + 13 stores of populations, FP64 / FP32
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E
 METRIC = "MLUPS and % of HBM roofline, FP32/batched vs plain FP64 GPU at stated error"
@@ -289,7 +290,9 @@ def copy_bandwidth():
 
 
 def cpu_baseline(n, budget_s):
-    """The FP64 CPU oracle on the same workload, for about budget_s seconds."""
+    """The FP64 CPU oracle on the same workload, for about budget_s seconds.
+    Returns the baseline record, the number of steps and the oracle's moments
+    (rho, ux, uy, T) after them (the reference of the error report)."""
     import oracle
     from paper_1401_0188_amd import workloads
     p = oracle.params()
@@ -303,8 +306,44 @@ def cpu_baseline(n, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or el / steps * (steps + 1) > 2.5 * budget_s:
             break
-    return dict(value=round(n * n * steps / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
-                sample="%d steps of the %dx%d periodic shear + acoustic wave, FP64 oracle, %.1f s" % (steps, n, n, el))
+    rec = dict(value=round(n * n * steps / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+               sample="%d steps of the %dx%d periodic shear + acoustic wave, FP64 oracle, %.1f s" % (steps, n, n, el))
+    om = oracle.moments(f, p)
+    del f
+    return rec, steps, om
+
+
+def final_moments(precision, n, launch, steps, graph_k):
+    """Moments (rho, ux, uy, T) on the host after `steps` steps of the wave in
+    the given launch configuration (outside any timed region)."""
+    import torch
+
+    from paper_1401_0188_amd import lbm13, workloads
+    lat = lbm13.Lattice(n, n, precision)
+    lat.set_tile(*launch["tile"])
+    lat.set_fused_tile(*launch["fused_tile"])
+    lat.set_steps_per_launch(launch["steps_per_launch"])
+    lat.set_interior_kernel(launch["interior_kernel"])
+    lat.set_params()
+    lat.init_moments(*workloads.shear_acoustic(n))
+    if graph_k and steps >= graph_k:
+        lat.use_graph(graph_k)
+    lat.step(steps)
+    m = [t.cpu().numpy() for t in lat.moments()]
+    lat.destroy()
+    del lat
+    torch.cuda.empty_cache()
+    return m
+
+
+def moment_errors(got, ref):
+    """Max relative error of rho and T, max absolute error of u (the measures of
+    the stated bounds: FP64 <= 1e-12, FP32 <= 1e-5)."""
+    import numpy as np
+    rho = float(np.abs(got[0] - ref[0]).max() / np.abs(ref[0]).max())
+    u = float(max(np.abs(got[1] - ref[1]).max(), np.abs(got[2] - ref[2]).max()))
+    T = float(np.abs(got[3] - ref[3]).max() / np.abs(ref[3]).max())
+    return {"rho_rel": rho, "u_abs": u, "T_rel": T}
 
 
 def roofline(nodes, kernel_ms, precision, traffic=None, spl=1):
@@ -348,6 +387,26 @@ def cpu_baseline_spec(spec, budget_s):
                     steps, spec["nx"], spec["ny"], el))
 
 
+def batch_final_moments(specs, precision, cfg, steps, graph_k):
+    """Moments of every domain on the host after `steps` steps of a batch in the
+    given launch configuration (outside any timed region)."""
+    import torch
+    b = build_batch(specs, precision)
+    if cfg:
+        b.set_tile(*cfg["tile"])
+        b.set_fused_tile(*cfg["fused_tile"])
+        b.set_interior_kernel(cfg["interior_kernel"])
+        b.set_steps_per_launch(cfg["steps_per_launch"])
+    if graph_k and steps >= graph_k:
+        b.use_graph(graph_k)
+    b.step(steps)
+    out = [[t.cpu().numpy() for t in b.moments(i)] for i in range(len(specs))]
+    b.destroy()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main_batched(args, copy_gbps):
     from paper_1401_0188_amd import lbm13
     specs = cavity_specs() if args.workload == "cavities64" else channel_specs()
@@ -364,6 +423,24 @@ def main_batched(args, copy_gbps):
     if not args.no_cpu:
         big = max(range(len(specs)), key=lambda i: specs[i]["nx"] * specs[i]["ny"])
         cpu = cpu_baseline_spec(specs[big], args.cpu_seconds)
+    err = None
+    if not args.no_accuracy:
+        # stated error, outside the timed region: every domain of the FP32 batch in
+        # the timed configuration against the same domains run as an FP64 batch
+        log("batched fp32 against fp64 after %d steps" % ACCURACY_STEPS)
+        ref = batch_final_moments(specs, lbm13.FP64, dict(r32["cfg"], fused_tile=(32, 16)), ACCURACY_STEPS, graph_k)
+        got = batch_final_moments(specs, lbm13.FP32_DEV, r32["cfg"], ACCURACY_STEPS, graph_k)
+        per = [moment_errors(g, r) for g, r in zip(got, ref)]
+        spread = [float(r[3].max() - r[3].min()) for r in ref]  # the T range of each FP64 domain
+        del got, ref
+        worst = max(range(len(per)), key=lambda i: max(per[i].values()))
+        err = {"bounds": {"fp32": 1e-5}, "fp32_vs_fp64_gpu": {
+            "steps": ACCURACY_STEPS, "rho_rel": max(e["rho_rel"] for e in per), "u_abs": max(e["u_abs"] for e in per),
+            "T_rel": max(e["T_rel"] for e in per), "domains": len(per),
+            "domains_over_bound": sum(1 for e in per if max(e.values()) > 1e-5),
+            "worst_domain": dict(index=worst, nx=specs[worst]["nx"], ny=specs[worst]["ny"],
+                                 E0=specs[worst]["kw"].get("E0", -2.0), T_range=spread[worst],
+                                 **per[worst], **specs[worst]["info"])}}
     clamped = sum(1 for s in specs if s["info"].get("clamped"))
     nonfinite = sum(1 for d in r32["diag"] if d["nonfinite"] > 0)
     return {
@@ -382,6 +459,7 @@ def main_batched(args, copy_gbps):
         "kernel_ms_per_launch": round(r32["kernel_ms_per_launch"], 5),
         "copy_GBps": round(copy_gbps, 1),
         "domains_nonfinite": nonfinite,
+        "error": err,
         "kernel_source_sha": kernel_sha(),
     }
 
@@ -398,6 +476,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the error report (timed forms against the oracle and FP32 against FP64)")
     ap.add_argument("--tune-steps", type=int, default=40,
                     help="steps per candidate of the launch autotuner for the wave forms (0: fixed configuration)")
     ap.add_argument("--launch-fp32", type=json.loads, metavar="JSON",
@@ -447,9 +527,27 @@ def main():
     log("fp64 one step per launch: %.1f MLUPS, kernel %.4f ms" % (r64p["mlups"], r64p["kernel_ms_per_launch"]))
 
     cpu = None
+    err = None
     if not args.no_cpu:
         log("cpu baseline (oracle) for about %.0f s" % args.cpu_seconds)
-        cpu = cpu_baseline(n, args.cpu_seconds)
+        cpu, cpu_steps, om = cpu_baseline(n, args.cpu_seconds)
+    if not args.no_accuracy:
+        # stated error of the timed forms, outside the timed region: against the
+        # oracle's state after the baseline's steps, and FP32 against FP64 on the
+        # GPU after 10^4 steps
+        err = {"bounds": {"fp64": 1e-12, "fp32": 1e-5}}
+        if cpu is not None:
+            log("error against the oracle after %d steps" % cpu_steps)
+            err["vs_oracle"] = {"steps": cpu_steps,
+                                "fp32": moment_errors(final_moments(lbm13.FP32_DEV, n, r32["launch"], cpu_steps, 0), om),
+                                "fp64": moment_errors(final_moments(lbm13.FP64, n, r64["launch"], cpu_steps, 0), om)}
+            del om
+        log("fp32 against fp64 after %d steps" % ACCURACY_STEPS)
+        m64 = final_moments(lbm13.FP64, n, r64["launch"], ACCURACY_STEPS, graph_k)
+        err["fp32_vs_fp64_gpu"] = dict(
+            steps=ACCURACY_STEPS, **moment_errors(final_moments(lbm13.FP32_DEV, n, r32["launch"], ACCURACY_STEPS,
+                                                                graph_k), m64))
+        del m64
 
     roof32 = roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, measured_traffic("fp32", r32["launch"]),
                       spl=r32["spl"])
@@ -489,6 +587,7 @@ def main():
         "copy_GBps": round(copy_gbps, 1),
         "frac_of_copy": round(roof32["achieved"] / copy_gbps, 4),
         "mass_drift": {"fp32": r32["mass_drift"], "fp64": r64["mass_drift"], "fp64_plain": r64p["mass_drift"]},
+        "error": err,
         "kernel_source_sha": kernel_sha(),
     }
     print(json.dumps(out), flush=True)
