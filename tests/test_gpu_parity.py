@@ -403,40 +403,54 @@ def test_batch_matches_oracle_per_domain():
 
 # --------------------------------------------------------------------------- runtime
 
-def test_graph_replay_is_bit_exact_with_direct_steps():
+@pytest.mark.parametrize("spl,k,odd", [(1, 8, 3), (2, 8, 2), (3, 6, 3)])
+def test_graph_replay_is_bit_exact_with_direct_steps(spl, k, odd):
+    """Graph replays against direct launches of the same launch sequence (a
+    graph of k steps is the launches of lbm13_step(k)); an odd number of
+    launches outside the graphs switches to the graph of the other buffer
+    parity; walls, so the side array's buffers flip with the states."""
     lbm13 = _lb()
     import torch
-    say("graph replay vs direct launches")
+    say("graph replay vs direct launches, %d steps per launch, graphs of %d" % (spl, k))
     fields = workloads.cavity_fields(128, ny=96, seed=3)
     sides = lbm13.make_sides((2, 2, 1, 1), (0, 0, 0, 0), (-1.995, -2.005, 0, 0))
     a = lbm13.Lattice(128, 96, lbm13.FP32_DEV)
+    a.set_steps_per_launch(spl)
     a.set_params(sides=sides, g=(0.0, -0.05))
     a.init_moments(*fields)
-    a.step(40)
+    for _ in range(5):
+        a.step(k)
     ref = a.get_state().cpu().numpy()
     b = lbm13.Lattice(128, 96, lbm13.FP32_DEV)
+    b.set_steps_per_launch(spl)
     b.set_params(sides=sides, g=(0.0, -0.05))
     b.init_moments(*fields)
-    b.use_graph(8)
+    b.use_graph(k)
     for _ in range(5):
-        b.step(8)
+        b.step(k)
         torch.cuda.synchronize()
         _ = [t.sum().item() for t in b.moments()]  # eager work between replays
-    assert b.steps_done() == 40
+    assert b.steps_done() == 5 * k
     assert np.array_equal(b.get_state().cpu().numpy(), ref)
-    b.step(3)  # odd remainder through direct launches, then graphs of the other parity
-    b.step(16)
-    a.step(19)
+    b.step(odd)  # one launch outside the graphs, then graphs of the other parity
+    b.step(2 * k)
+    a.step(odd)
+    a.step(k)
+    a.step(k)
     assert np.array_equal(b.get_state().cpu().numpy(), a.get_state().cpu().numpy())
 
 
+@pytest.mark.parametrize("spl", [1, 3])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_checkpoint_resume_is_bit_exact(precision):
+def test_checkpoint_resume_is_bit_exact(precision, spl):
+    """A saved state resumes bit-exactly, the wall side array refilled from it
+    by the same arithmetic the steps use."""
     lbm13 = _lb()
-    say("checkpoint / resume precision %d" % precision)
+    say("checkpoint / resume precision %d, %d steps per launch" % (precision, spl))
     fields = workloads.cavity_fields(64, ny=48, seed=12)
     sides = lbm13.make_sides((2, 2, 1, 1), (0.01, 0, 0, 0), (-1.995, -2.005, 0, 0))
     lat = lbm13.Lattice(64, 48, precision)
+    lat.set_steps_per_launch(spl)
     lat.set_params(sides=sides, g=(0.0, -0.01))
     lat.init_moments(*fields)
     lat.step(30)
