@@ -37,7 +37,7 @@ template <typename R>
 hipError_t launch_fourier(int, int, const R*, const Dom<R>*, int, int, const Tile*, int, int, double*, double*,
                           hipStream_t);
 template <typename R>
-hipError_t launch_step3(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int, hipStream_t);
+hipError_t launch_step3(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int, bool, hipStream_t);
 template <typename R>
 hipError_t launch_init(int, int, R*, const Dom<R>*, int, const double*, const double*, const double*, const double*,
                        const double*, hipStream_t);
@@ -220,6 +220,7 @@ struct lbm13_batch {
     int nbulk = 0, nedge = 0;
     int nfint = 0, nfedge = 0;            // interior / edge tiles of the fused table
     int n3int = 0, n3edge = 0;            // interior / edge tiles of the three-step table
+    bool sourced = true;                  // some domain has a body force or an energy source
     int split = 1;                        // 1: interior tiles run the compact-LDS kernel
     int tile_x = 64, tile_y = 8;
     int cur = 0;                          // buffer holding the current state
@@ -295,6 +296,18 @@ void set_tile_ranges(lbm13_batch* b) {
         dom_host<R>(b, d)->ntiles = n;
         t += n;
     }
+}
+
+// Whether some domain with parameters has a body force or an energy source
+// (the three-step window kernel drops those terms otherwise).
+template <typename R>
+bool any_sources(lbm13_batch* b) {
+    for (int d = 0; d < b->count; ++d) {
+        if (!b->has_params[d]) continue;
+        const Dom<R>* D = dom_host<R>(b, d);
+        if (D->F0x_d != 0.0 || D->F0y_d != 0.0 || D->gx_d != 0.0 || D->gy_d != 0.0 || D->QE_d != 0.0) return true;
+    }
+    return false;
 }
 
 // Rebuild the tile tables for the current tile shape and sides; uploads the
@@ -386,6 +399,7 @@ int rebuild(lbm13_batch* b) {
     if ((long long)b->lines.size() > b->L.nlines_max) return fail(b, LBM13_EINVAL, "wall line table overflow");
     b->nbulk = (int)bulk.size();
     b->nedge = (int)edge.size();
+    b->sourced = b->precision == LBM13_FP64 ? any_sources<double>(b) : any_sources<float>(b);
     if (b->precision == LBM13_FP64) set_tile_ranges<double>(b);
     else set_tile_ranges<float>(b);
     hipError_t e;
@@ -543,15 +557,16 @@ hipError_t launch_three_steps(lbm13_batch* b, int from, hipStream_t s) {
     R* dst = buf<R>(b, 1 - from);
     if (b->n3int == 0 || b->n3edge == 0 || !b->aux)
         return lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->n3int, b->n3edge, side,
-                                      from, s);
+                                      from, b->sourced, s);
     hipError_t e = hipEventRecord(b->ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->aux, b->ev_fork, 0);
     if (e == hipSuccess)
         e = lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles + b->n3int, 0, b->n3edge, side,
-                                   from, b->aux);
+                                   from, b->sourced, b->aux);
     if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->aux);
     if (e == hipSuccess)
-        e = lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->n3int, 0, side, from, s);
+        e = lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->n3int, 0, side, from,
+                                   b->sourced, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join, 0);
     return e;
 }

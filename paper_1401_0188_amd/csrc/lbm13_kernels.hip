@@ -63,8 +63,9 @@ __device__ __forceinline__ double reciprocal(double x) {
 //   m = M g; Delta_k = s_k (m_k - m_k^eq) on the nine non-conserved moments;
 //   j* = j + F (secs. 5, 8); E* = E + Q_E (sec. 9); g* = g - M^T D^-1 Delta.
 // Pairs (i, opposite of i) give sums s (even moments) and differences d (odd
-// moments); the inverse splits the same way.
-template <typename R>
+// moments); the inverse splits the same way.  Sourced = false drops the body
+// force and energy-source terms, for launches whose domains have neither.
+template <typename R, bool Sourced = true>
 __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
     const R s13 = g[1] + g[3], d13 = g[1] - g[3];
     const R s24 = g[2] + g[4], d24 = g[2] - g[4];
@@ -93,33 +94,48 @@ __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
     const R aXX = D.kX * (XX - (jx * jx - jy * jy) * inv_rho);
     const R aXY = D.kY * (XY - jx * jy * inv_rho);
     const R aXXe = D.kXe * XXe;
-    // odd moments: the force enters as Delta_j = -F
-    const R bjx = D.fjx + D.gjx * rho, bjy = D.fjy + D.gjy * rho;
+    // odd moments
     const R bqx = D.kq * (qx - jx * fq), bqy = D.kq * (qy - jy * fq);
     const R brx = D.kr * (rx - jx * fr), bry = D.kr * (ry - jy * fr);
 
     // isotropic even part: eps and varpi relaxed (each a linear form of the
     // class sums), mapped back by the integer rows of M so that the update
-    // keeps sum g and the E moment exactly; the energy source enters as
-    // Delta_E = -Q_E (sec. 9)
+    // keeps sum g and the E moment exactly
     const R aeps = D.aeps[0] * g[0] + D.aeps[1] * S1 + D.aeps[2] * S2 + D.aeps[3] * S3;
     const R avp = D.avp[0] * g[0] + D.avp[1] * S1 + D.avp[2] * S2 + D.avp[3] * S3;
-    const R e0 = R(140) * aeps - R(12) * avp + D.eQ[0];
-    const R ec1 = R(-2) * aeps + R(8) * avp + D.eQ[1];
-    const R ec5 = R(-67) * aeps - R(6) * avp + D.eQ[2];
-    const R ec9 = R(34) * aeps + avp + D.eQ[3];
+    R e0 = R(140) * aeps - R(12) * avp;
+    R ec1 = R(-2) * aeps + R(8) * avp;
+    R ec5 = R(-67) * aeps - R(6) * avp;
+    R ec9 = R(34) * aeps + avp;
+    R o1, o2, o5, o6, o9, o10;
+    if constexpr (Sourced) {
+        // the energy source enters as Delta_E = -Q_E (sec. 9), the force as
+        // Delta_j = -F (secs. 5, 8)
+        e0 += D.eQ[0];
+        ec1 += D.eQ[1];
+        ec5 += D.eQ[2];
+        ec9 += D.eQ[3];
+        const R bjx = D.fjx + D.gjx * rho, bjy = D.fjy + D.gjy * rho;
+        o1 = bjx - R(2) * bqx + R(4) * brx;
+        o2 = bjy - R(2) * bqy + R(4) * bry;
+        o5 = bjx + bjy - bqx - bqy - R(3) * (brx + bry);
+        o6 = -bjx + bjy + bqx - bqy + R(3) * (brx - bry);
+        o9 = R(2) * (bjx + bqx) + brx;
+        o10 = R(2) * (bjy + bqy) + bry;
+    } else {
+        o1 = R(4) * brx - R(2) * bqx;
+        o2 = R(4) * bry - R(2) * bqy;
+        o5 = -(bqx + bqy) - R(3) * (brx + bry);
+        o6 = bqx - bqy + R(3) * (brx - bry);
+        o9 = R(2) * bqx + brx;
+        o10 = R(2) * bqy + bry;
+    }
     const R e1 = ec1 + aXX - R(4) * aXXe;
     const R e2 = ec1 - aXX + R(4) * aXXe;
     const R e5 = ec5 + aXY;
     const R e6 = ec5 - aXY;
     const R e9 = ec9 + R(4) * aXX + aXXe;
     const R e10 = ec9 - R(4) * aXX - aXXe;
-    const R o1 = bjx - R(2) * bqx + R(4) * brx;
-    const R o2 = bjy - R(2) * bqy + R(4) * bry;
-    const R o5 = bjx + bjy - bqx - bqy - R(3) * (brx + bry);
-    const R o6 = -bjx + bjy + bqx - bqy + R(3) * (brx - bry);
-    const R o9 = R(2) * (bjx + bqx) + brx;
-    const R o10 = R(2) * (bjy + bqy) + bry;
 
     g[0] -= e0;
     g[1] -= e1 + o1;
@@ -804,7 +820,8 @@ void step2_interior_kernel(const R* __restrict__ src, R* __restrict__ dst,
 // up to 1024 (FP32) or 512 (FP64) nodes take one thread per node, with the
 // registers of the occupancy the LDS allows (FP32 64x16: two 1024-thread
 // workgroups, eight waves per SIMD; FP64 32x16: two 512-thread workgroups).
-template <typename R, int TW, int TH, int NT>
+// Sourced = false: no domain of the launch has a body force or energy source.
+template <typename R, int TW, int TH, int NT, bool Sourced>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
     lds_waves_per_eu((2 + 13 * (TW + 4) * (TH + 4)) * (int)sizeof(R), NT)))) void step3_kernel(const R* __restrict__ src, R* __restrict__ dst,
                                                    const Dom<R>* __restrict__ doms,
@@ -855,7 +872,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int k = 0; k < NI1; ++k) {
         if (tid + k * NT < N1) {
-            if (D.collide) collide(g[k], D);
+            if (D.collide) collide<R, Sourced>(g[k], D);
             const int lx = l1x[k], ly = l1y[k], base = ly * W2 + lx;
 #define LBM13_WINDOW1(I)                                                                                   \
     if ((unsigned)(lx - 2 + kVX[I]) < (unsigned)W2 && (unsigned)(ly - 2 + kVY[I]) < (unsigned)H2)          \
@@ -876,7 +893,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
         if (r < N2) {
 #pragma unroll
             for (int i = 0; i < 13; ++i) h[k][i] = lds[kLead + ((i + 3) % 13) * N2 + r];
-            if (D.collide) collide(h[k], D);
+            if (D.collide) collide<R, Sourced>(h[k], D);
         }
     }
     __syncthreads();
@@ -904,7 +921,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
         R q[13];
 #pragma unroll
         for (int i = 0; i < 13; ++i) q[i] = lds[kLead + ((i + 3) % 13) * N3 + r];
-        if (D.collide) collide(q, D);
+        if (D.collide) collide<R, Sourced>(q, D);
 #pragma unroll
         for (int i = 0; i < 13; ++i) buffer_store_nt<R>(q[i], out, c, (unsigned)(i * S * es));
     }
@@ -1545,15 +1562,19 @@ hipError_t launch_step2(int tw, int th, const R* src, R* dst, const Dom<R>* doms
 
 // Three steps per launch: interior tiles tiles[0, nint) (flag 2, plus 4 where
 // the region wraps) on step3_kernel, the other tiles tiles[nint, nint + nedge)
-// on step3_wall_kernel.
+// on step3_wall_kernel; sourced = false when no domain has a body force or an
+// energy source.
 template <typename R>
 hipError_t launch_step3(int tw, int th, const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int nint,
-                        int nedge, R* side, int from, hipStream_t s) {
+                        int nedge, R* side, int from, bool sourced, hipStream_t s) {
 #define LBM13_STEP3(T, TW, TH)                                                                                 \
     if constexpr (std::is_same<R, T>::value) {                                                                 \
         if (tw == TW && th == TH) {                                                                            \
             constexpr int NT = sizeof(R) == 4 ? (TW * TH < 256 ? 256 : TW * TH) : (TW * TH >= 512 ? 512 : 256); \
-            if (nint > 0) step3_kernel<R, TW, TH, NT><<<nint, NT, 0, s>>>(src, dst, doms, tiles, nint);       \
+            if (nint > 0 && sourced)                                                                           \
+                step3_kernel<R, TW, TH, NT, true><<<nint, NT, 0, s>>>(src, dst, doms, tiles, nint);            \
+            else if (nint > 0)                                                                                 \
+                step3_kernel<R, TW, TH, NT, false><<<nint, NT, 0, s>>>(src, dst, doms, tiles, nint);           \
             if (nedge > 0)                                                                                     \
                 step3_wall_kernel<R, TW, TH, NT>                                                               \
                     <<<nedge, NT, 0, s>>>(src, dst, doms, tiles + nint, nedge, side, from);                    \
@@ -1616,7 +1637,7 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
     template hipError_t launch_step2<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int,     \
                                         hipStream_t);                                                             \
     template hipError_t launch_step3<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int,     \
-                                        hipStream_t);                                                             \
+                                        bool, hipStream_t);                                                       \
     template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, int,          \
                                             hipStream_t);                                                         \
     template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, R*,     \
