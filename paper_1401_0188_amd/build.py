@@ -43,5 +43,23 @@ def build(extra=(), out: str = LIB, verbose: bool = False) -> str:
     return out
 
 
+EXAMPLE_SRC = os.path.join(HERE, "examples", "c_api_example.cpp")
+EXAMPLE = os.path.join(HERE, "examples", "c_api_example")
+
+
+def build_example(out: str = EXAMPLE, verbose: bool = False) -> str:
+    """Compile the standalone C-ABI example against the built library (no
+    PyTorch): hipMalloc'd workspace, the library's calls, a decay check."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17", "-I" + os.path.join(ROOT, "include"), EXAMPLE_SRC,
+           "-L" + HERE, "-llbm13", "-Wl,-rpath," + HERE, "-Wl,-rpath,$ORIGIN/..", "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(extra=sys.argv[1:], verbose=True))
+    print(build_example(verbose=True))

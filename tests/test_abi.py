@@ -88,3 +88,11 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     assert L.lbm13_step(None, 1) == lbm13.EINVAL
     assert L.lbm13_destroy(None) == lbm13.EINVAL
     assert L.lbm13_last_error(None) == b"null context"
+
+
+def test_c_api_example_builds_without_torch(tmp_path):
+    """include/lbm13.h is a self-sufficient C ABI: a C++ program that uses only
+    HIP and the library's calls compiles and links against liblbm13.so."""
+    from paper_1401_0188_amd import build
+    out = build.build_example(out=str(tmp_path / "c_api_example"))
+    assert os.path.getsize(out) > 0

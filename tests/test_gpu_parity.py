@@ -13,6 +13,7 @@ Bars:
 """
 from __future__ import annotations
 
+import os
 import sys
 
 import numpy as np
@@ -204,6 +205,65 @@ def test_full_size_4096_matches_oracle(precision):
         assert_fp64(gs, gm, fs, om)
     else:
         assert_fp32(gm, om, tol=1e-6)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("nx,ny,axis,precision,spl", [
+    (65536, 64, "x", 0, 3), (65536, 64, "x", 1, 1), (64, 65536, "y", 1, 3), (64, 65536, "y", 0, 1),
+    (12800, 12800, "x", 1, 3)])
+def test_maximum_sizes(nx, ny, axis, precision, spl):
+    """The layout's limits: sides of 65536 and 12800^2 nodes (13 planes just
+    under 2^31 elements).  A wave along one axis on a periodic domain stays
+    uniform along the other, so every node equals the oracle's on a 4-wide
+    periodic strip; sampled rows (columns) are compared with it."""
+    lbm13 = _lb()
+    say("maximum size %dx%d precision %d, %d steps per launch" % (nx, ny, precision, spl))
+    n = nx if axis == "x" else ny
+    k = 2.0 * np.pi / n
+    s = 0.5 * (1.0 + np.cos(k * np.arange(n)))  # smooth, O(1) variation along the axis
+    line = (1.0 + 0.01 * s, 0.02 * s, 0.01 * np.sin(k * np.arange(n)), -2.0 + 0.005 * s)
+
+    def fields(nx_, ny_):
+        if axis == "x":
+            return tuple(np.broadcast_to(a[None, :], (ny_, nx_)).copy() for a in line)
+        return tuple(np.broadcast_to(a[:, None], (ny_, nx_)).copy() for a in line)
+
+    steps = 6
+    strip = (nx, 4) if axis == "x" else (4, ny)
+    po = oracle.params()
+    om = oracle.moments(oracle.run(oracle.init(*fields(*strip), po), po, oracle.sides(), steps), po)
+    lat = lbm13.Lattice(nx, ny, precision)
+    lat.set_fused_tile(32, 16)
+    lat.set_steps_per_launch(spl)
+    lat.set_params()
+    lat.init_moments(*fields(nx, ny))
+    lat.step(steps)
+    gm = lat.moments()
+    picks = [0, 1, (ny if axis == "x" else nx) // 2, (ny if axis == "x" else nx) - 1]
+    for q in picks:
+        got = [(t[q] if axis == "x" else t[:, q]).cpu().numpy() for t in gm]
+        ref = [(m[q % 4] if axis == "x" else m[:, q % 4]) for m in om]
+        if precision == 0:
+            assert np.abs(got[0] - ref[0]).max() <= 1e-12 * np.abs(ref[0]).max()
+            assert max(np.abs(got[1] - ref[1]).max(), np.abs(got[2] - ref[2]).max()) <= 1e-12
+            assert np.abs(got[3] - ref[3]).max() <= 1e-12 * np.abs(ref[3]).max()
+        else:
+            assert_fp32(got, ref)
+    del gm
+    lat.destroy()
+
+
+def test_c_api_example_runs():
+    """The standalone C-ABI example (no PyTorch) runs a periodic shear wave in
+    three-step launches and checks its decay against exp(-nu k^2 t)."""
+    import subprocess
+    from paper_1401_0188_amd import build
+    say("standalone C-ABI example")
+    assert os.path.exists(build.EXAMPLE), "run __graft_entry__.build() first"
+    r = subprocess.run([build.EXAMPLE], capture_output=True, text=True, timeout=120)
+    print(r.stdout, r.stderr)
+    assert r.returncode == 0, (r.stdout, r.stderr)
+    assert "relative difference" in r.stdout
 
 
 def test_large_domain_beyond_32bit_plane_offsets():
