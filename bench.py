@@ -464,12 +464,104 @@ def main_batched(args, copy_gbps):
     }
 
 
+def small_case(workload):
+    """The small configurations, whose state fits in the caches: the 32^2
+    periodic wave in FP64 (1000 steps) and the 256^2 heated cavity at Ra = 1e5,
+    Pr = 0.71 in FP64 and FP32 (10^4 steps)."""
+    from paper_1401_0188_amd import workloads
+    if workload == "wave32":
+        return dict(n=32, steps=1000, forms=(0,), fields=workloads.periodic_wave(32), kinds=(0, 0, 0, 0),
+                    T_w=(0, 0, 0, 0), kw={}, desc="periodic 32x32 nonlinear wave (rho, ux cosine)")
+    from paper_1401_0188_amd import lbm13
+    n, Ra, Pr, s_XX = 256, 1e5, 0.71, 1.7
+    st, d = lbm13.derive(Pr=Pr, s_XX=s_XX)
+    cf = workloads.cavity_forcing(n, Ra, Pr, d["nu"], d["kappa"])
+    return dict(n=n, steps=10000, forms=(0, 1), fields=workloads.cavity_fields(n, seed=0, dT=cf["dT"]),
+                kinds=(2, 2, 1, 1), T_w=(-2 + cf["dT"] / 2, -2 - cf["dT"] / 2, 0, 0),
+                kw=dict(Pr=Pr, s_XX=s_XX, g=(0.0, -cf["g"])),
+                desc="heated cavity 256x256, Ra %.3g (dT %.3g), Pr 0.71, hot West / cold East, adiabatic S/N" % (
+                    cf["Ra"], cf["dT"]))
+
+
+def cpu_baseline_small(c):
+    """The FP64 CPU oracle over a whole small configuration: its rate, and its
+    moments after the configuration's steps (the reference of the error)."""
+    import oracle
+    kw = dict(c["kw"])
+    g = kw.pop("g", (0.0, 0.0))
+    po = oracle.params(gx=g[0], gy=g[1], **kw)
+    so = oracle.sides(c["kinds"], (0, 0, 0, 0), c["T_w"])
+    t0 = time.perf_counter()
+    f = oracle.run(oracle.init(*c["fields"], po), po, so, c["steps"])
+    el = time.perf_counter() - t0
+    om = oracle.moments(f, po)
+    rec = dict(value=round(c["n"] * c["n"] * c["steps"] / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(),
+               kind="oracle", sample="the whole run, %d steps, %.1f s" % (c["steps"], el))
+    return rec, om
+
+
+def main_small(args, copy_gbps):
+    """A small configuration: each form timed over the configuration's steps
+    (autotuned launch), its error against the oracle after the same steps, and
+    the oracle's own rate on the host."""
+    import torch
+
+    from paper_1401_0188_amd import lbm13
+    c = small_case(args.workload)
+    n, steps = c["n"], c["steps"]
+    log("%s: oracle, %d steps" % (args.workload, steps))
+    cpu, om = cpu_baseline_small(c)
+    forms = {}
+    for prec in c["forms"]:
+        lat = lbm13.Lattice(n, n, prec)
+        lat.set_params(sides=lbm13.make_sides(c["kinds"], (0, 0, 0, 0), c["T_w"]), **c["kw"])
+        lat.init_moments(*c["fields"])
+        lat.autotune(12)
+        lat.init_moments(*c["fields"])
+        launch = lat.launch_config()
+        if not args.no_graph:
+            lat.use_graph(GRAPH_K)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        t1 = time.perf_counter()
+        a.record(lat.stream)
+        lat.step(steps)
+        b.record(lat.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        gm = [t.cpu().numpy() for t in lat.moments()]
+        forms["fp64" if prec == 0 else "fp32"] = {
+            "value": round(n * n * steps / wall / 1e6, 1), "unit": "MLUPS",
+            "kernel_ms_per_step": round(a.elapsed_time(b) / steps, 5), "launch": launch,
+            "error_vs_oracle": moment_errors(gm, om)}
+        lat.destroy()
+        del lat
+        torch.cuda.empty_cache()
+    head = forms["fp32"] if "fp32" in forms else forms["fp64"]
+    return {
+        "metric": METRIC, "value": head["value"], "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(n * n / head["value"] / 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if "fp32" in forms else "f64", "data": "synthetic",
+        "config": {"workload": c["desc"], "nx": n, "ny": n, "steps": steps,
+                   "note": "state resident in the L2 / MALL caches: no HBM roofline claim"},
+        "roofline": None,
+        "cpu_baseline": cpu,
+        "forms": forms,
+        "error": {"bounds": {"fp64": 1e-12, "fp32": 1e-5},
+                  "vs_oracle": {k: v["error_vs_oracle"] for k, v in forms.items()}, "steps": steps},
+        "copy_GBps": round(copy_gbps, 1),
+        "kernel_source_sha": kernel_sha(),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2040)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="wave4096", choices=["wave4096", "cavities64", "channels128"])
+    ap.add_argument("--workload", default="wave4096",
+                    choices=["wave4096", "cavities64", "channels128", "wave32", "cavity256"])
     ap.add_argument("--size", type=int, default=4096, help="side of the periodic wave (wave4096)")
     ap.add_argument("--diag-every", type=int, default=1000)
     ap.add_argument("--fp64-steps", type=int, default=-1, help="steps of the plain FP64 form")
@@ -499,6 +591,9 @@ def main():
 
     log("device copy bandwidth")
     copy_gbps = copy_bandwidth()
+    if args.workload in ("wave32", "cavity256"):
+        print(json.dumps(main_small(args, copy_gbps)), flush=True)
+        return
     if args.workload != "wave4096":
         print(json.dumps(main_batched(args, copy_gbps)), flush=True)
         return
