@@ -194,16 +194,17 @@ def build_batch(specs, precision):
     return b
 
 
-def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=True):
+def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=True, launch=None):
+    """`launch`: a fixed launch configuration (a `launch` object of an earlier run) instead of autotuning."""
     import torch
     b = build_batch(specs, precision)
-    tile = None
-    cfg = None
-    if autotune:
-        b.autotune(10)
-        cfg = b.launch_config()
-        b.destroy()
-        b = build_batch(specs, precision)  # fresh state after tuning
+    cfg = dict(launch) if launch else None
+    if autotune or cfg:
+        if not cfg:
+            b.autotune(10)
+            cfg = b.launch_config()
+            b.destroy()
+            b = build_batch(specs, precision)  # fresh state after tuning
         b.set_tile(*cfg["tile"])
         b.set_fused_tile(*cfg["fused_tile"])
         b.set_interior_kernel(cfg["interior_kernel"])
@@ -412,7 +413,7 @@ def main_batched(args, copy_gbps):
     specs = cavity_specs() if args.workload == "cavities64" else channel_specs()
     graph_k = 0 if args.no_graph else GRAPH_K
     log("%s: %d domains, batched fp32-deviation, %d steps" % (args.workload, len(specs), args.steps))
-    r32 = run_batch(specs, lbm13.FP32_DEV, args.steps, args.warmup, args.diag_every, graph_k)
+    r32 = run_batch(specs, lbm13.FP32_DEV, args.steps, args.warmup, args.diag_every, graph_k, launch=args.launch_fp32)
     log("batched fp32: %.1f MLUPS, kernel %.4f ms per launch, config %s" % (r32["mlups"], r32["kernel_ms_per_launch"],
                                                                           r32["cfg"]))
     fp64_steps = args.fp64_steps if args.fp64_steps >= 0 else max(1, args.steps // 4)
@@ -449,6 +450,7 @@ def main_batched(args, copy_gbps):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "%s: %d domains, %d nodes" % (args.workload, len(specs), r32["nodes"]),
                    "form": "fp32-deviation batched, one launch covers every domain", "launch": r32["cfg"],
+                   "launch_choice": "fixed" if args.launch_fp32 else "autotuned on this device",
                    "graph_steps": graph_k, "diag_every": args.diag_every, "clamped_domains": clamped},
         "roofline": roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, spl=r32["spl"]),
         "cpu_baseline": cpu,
@@ -573,7 +575,8 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=40,
                     help="steps per candidate of the launch autotuner for the wave forms (0: fixed configuration)")
     ap.add_argument("--launch-fp32", type=json.loads, metavar="JSON",
-                    help="fix the FP32 launch configuration (a `launch` object of an earlier run; no autotuning)")
+                    help="fix the FP32 launch configuration (a `launch` object of an earlier run; no autotuning); "
+                         "also for the batched workloads")
     ap.add_argument("--launch-fp64", type=json.loads, metavar="JSON",
                     help="fix the FP64 launch configuration (as --launch-fp32)")
     args = ap.parse_args()
