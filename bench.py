@@ -35,6 +35,7 @@ BYTES_PER_LU = {0: 208, 1: 104}  # 13 loads + 13 stores of populations, FP64 / F
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E
 METRIC = "MLUPS and % of HBM roofline, FP32/batched vs plain FP64 GPU at stated error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096_traffic.json")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step3_batched_traffic.json")
 # the sources that decide what the timed kernels do: the kernels, the descriptor
 # layout and the host code that builds the tile tables and launches
 KERNEL_SRC = [os.path.join(ROOT, "paper_1401_0188_amd", "csrc", f)
@@ -63,13 +64,13 @@ def launch_kernels(launch):
     return (3, tuple(launch["fused_tile"]), bool(launch["interior_kernel"]))
 
 
-def measured_traffic(key, launch):
+def measured_traffic(key, launch, path=None):
     """HBM bytes per launch of the timed form from the committed rocprofv3
     counter runs, if they were taken on the current kernel source with the
     same kernels (the configuration the default run chose, or one of the
     alternates measured beside it); else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path or TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -347,7 +348,7 @@ def moment_errors(got, ref):
     return {"rho_rel": rho, "u_abs": u, "T_rel": T}
 
 
-def roofline(nodes, kernel_ms, precision, traffic=None, spl=1):
+def roofline(nodes, kernel_ms, precision, traffic=None, spl=1, bound=None):
     """Algorithmic bytes per launch (26 population moves per lattice update,
     spl updates per node per launch) over the launch's duration."""
     achieved = BYTES_PER_LU[precision] * nodes * spl / (kernel_ms * 1e-3) / 1e9
@@ -358,7 +359,9 @@ def roofline(nodes, kernel_ms, precision, traffic=None, spl=1):
     if spl > 1:
         out["note"] = ("%d steps per launch: the algorithmic bytes are those of %d single steps, the HBM bytes "
                        "moved are `traffic` (rocprofv3 counters)" % (spl, spl))
-        if spl == 3:
+        if bound:
+            out["note"] += "; " + bound
+        elif spl == 3:
             out["note"] += ("; on the wave the three-step kernel is bound by vector ALU issue (FP32) or latency "
                             "(FP64), profiles/step3_kernel_4096_counters.md")
     return out
@@ -452,7 +455,10 @@ def main_batched(args, copy_gbps):
                    "form": "fp32-deviation batched, one launch covers every domain", "launch": r32["cfg"],
                    "launch_choice": "fixed" if args.launch_fp32 else "autotuned on this device",
                    "graph_steps": graph_k, "diag_every": args.diag_every, "clamped_domains": clamped},
-        "roofline": roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, spl=r32["spl"]),
+        "roofline": roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, spl=r32["spl"],
+                             traffic=measured_traffic(args.workload, r32["cfg"], BATCH_TRAFFIC_FILE) if r32["cfg"] else None,
+                             bound="the general (wall) kernel is bound by vector ALU issue, "
+                                   "profiles/step3_wall_kernel_channels_counters.md"),
         "cpu_baseline": cpu,
         "fp64_sequential": {"value": round(r64["mlups"], 1), "unit": "MLUPS",
                             "ms_per_step": round(r64["ms_per_step"], 5), "steps": fp64_steps,
