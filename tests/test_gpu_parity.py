@@ -911,6 +911,72 @@ def test_three_steps_per_launch_walls(name, precision):
     lat.destroy()
 
 
+# Domains of 2 to 7 nodes a side (2 x 2 is the smallest the library takes):
+# every region wraps or is clamped several times over, and the reach-2 links
+# of a 2-node walled axis reverse against the wall on each side.
+TINY = [(2, 2), (2, 7), (7, 2), (3, 3), (5, 4)]
+TINY_SIDES = {
+    "periodic": ((0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0), dict(F0=(1e-5, -1e-5))),
+    "temperature_walls_x": ((2, 2, 0, 0), (0, 0, 0, 0), (-1.99, -2.01, 0, 0), dict(g=(0.0, -1e-4))),
+    "moving_adiabatic_y": ((0, 0, 1, 1), (0, 0, 0.02, 0), (0, 0, 0, 0), dict(F0=(1e-5, 0.0))),
+    "closed": ((2, 2, 1, 1), (0, 0, 0, -0.01), (-1.99, -2.01, 0, 0), dict(g=(0.0, -1e-4))),
+}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("spl", [1, 2, 3])
+def test_smallest_domains(spl, precision):
+    """The smallest domains in one-, two- and three-step launches against the
+    oracle: zero steps (the initial state), then 7 steps (a remainder after two-
+    and three-step launches)."""
+    for nx, ny in TINY:
+        fields = workloads.cavity_fields(nx, ny=ny, seed=7, dT=0.01)
+        for name, (kinds, u_t, T_w, extra) in TINY_SIDES.items():
+            for steps in (0, 7):
+                say("smallest domain %d x %d %s, %d steps, %d steps per launch, precision %d"
+                    % (nx, ny, name, steps, spl, precision))
+                lat, gs, gm, fs, om, *_ = run_both(nx, ny, fields, steps, kinds, u_t, T_w, precision=precision,
+                                                   spl=spl, **extra)
+                assert lat.steps_done() == steps
+                if precision == 0:
+                    assert_fp64(gs, gm, fs, om)
+                else:
+                    assert_fp32(gm, om)
+                lat.destroy()
+
+
+def test_smallest_domains_batched_with_large_ones():
+    """Tiny domains in one batch with larger ones, three steps per launch and
+    graph replay: each domain against the oracle."""
+    lbm13 = _lb()
+    cases = [(2, 2, "closed"), (96, 40, "temperature_walls_x"), (7, 2, "moving_adiabatic_y"), (3, 3, "periodic"),
+             (33, 70, "closed"), (2, 7, "temperature_walls_x")]
+    for precision in (0, 1):
+        say("batch of tiny and large domains precision %d" % precision)
+        b = lbm13.Batch([(c[0], c[1]) for c in cases], precision)
+        b.set_steps_per_launch(3)
+        fields = []
+        for i, (nx, ny, name) in enumerate(cases):
+            kinds, u_t, T_w, extra = TINY_SIDES[name]
+            po, pl = params_pair(**dict(extra))
+            b.set_params(i, sides=lbm13.make_sides(kinds, u_t, T_w), **pl)
+            fields.append(workloads.cavity_fields(nx, ny=ny, seed=40 + i, dT=0.01))
+            b.init_moments(i, *fields[-1])
+        b.use_graph(6)
+        b.step(20)
+        for i, (nx, ny, name) in enumerate(cases):
+            kinds, u_t, T_w, extra = TINY_SIDES[name]
+            po, pl = params_pair(**dict(extra))
+            f = oracle.run(oracle.init(*fields[i], po), po, oracle.sides(kinds, u_t, T_w), 20)
+            gm = [t.cpu().numpy() for t in b.moments(i)]
+            om = oracle.moments(f, po)
+            if precision == 0:
+                assert_fp64(b.get_state(i).cpu().numpy(), gm, oracle.collide(f, po), om)
+            else:
+                assert_fp32(gm, om)
+        b.destroy()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_every_three_step_tile_shape(precision):
     """Every three-step tile shape on a closed moving-wall cavity (no interior
