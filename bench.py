@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -291,6 +292,40 @@ def copy_bandwidth():
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def host_cpu():
+    """Model name of the host CPU the oracle runs on."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def one_thread(rec, step, nodes, budget_s):
+    """Adds to an oracle baseline record its rate on one host thread: `step`
+    advances the oracle by one step, timed for about budget_s (at least once)."""
+    import oracle
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            step()
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or el / steps * (steps + 1) > 2 * budget_s:
+                break
+    finally:
+        oracle.set_num_threads(threads)
+    rec["value_1_thread"] = round(nodes * steps / el / 1e6, 3)
+    rec["sample_1_thread"] = "%d steps, %.1f s" % (steps, el)
+    rec["cpu"] = host_cpu()
+    return rec
+
+
 def cpu_baseline(n, budget_s):
     """The FP64 CPU oracle on the same workload, for about budget_s seconds.
     Returns the baseline record, the number of steps and the oracle's moments
@@ -311,7 +346,12 @@ def cpu_baseline(n, budget_s):
     rec = dict(value=round(n * n * steps / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
                sample="%d steps of the %dx%d periodic shear + acoustic wave, FP64 oracle, %.1f s" % (steps, n, n, el))
     om = oracle.moments(f, p)
-    del f
+    state = [f]
+
+    def advance():
+        state[0] = oracle.step(state[0], p, s)
+    one_thread(rec, advance, n * n, budget_s / 2)
+    del f, state
     return rec, steps, om
 
 
@@ -386,9 +426,14 @@ def cpu_baseline_spec(spec, budget_s):
         if el >= budget_s:
             break
     n = spec["nx"] * spec["ny"]
-    return dict(value=round(n * steps / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
-                sample="%d steps of one %dx%d domain of the workload, FP64 oracle, %.1f s" % (
-                    steps, spec["nx"], spec["ny"], el))
+    rec = dict(value=round(n * steps / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+               sample="%d steps of one %dx%d domain of the workload, FP64 oracle, %.1f s" % (
+                   steps, spec["nx"], spec["ny"], el))
+    state = [f]
+
+    def advance():
+        state[0] = oracle.step(state[0], p, s)
+    return one_thread(rec, advance, n, budget_s / 2)
 
 
 def batch_final_moments(specs, precision, cfg, steps, graph_k):
@@ -505,6 +550,11 @@ def cpu_baseline_small(c):
     om = oracle.moments(f, po)
     rec = dict(value=round(c["n"] * c["n"] * c["steps"] / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(),
                kind="oracle", sample="the whole run, %d steps, %.1f s" % (c["steps"], el))
+    state = [f]
+
+    def advance():
+        state[0] = oracle.step(state[0], po, so)
+    one_thread(rec, advance, c["n"] * c["n"], min(3.0, max(el, 0.05)))
     return rec, om
 
 

@@ -91,6 +91,7 @@ def lib():
         L.or13_diagnostics.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(Params),
                                        ctypes.POINTER(Sides), dp]
         L.or13_num_threads.restype = ctypes.c_int
+        L.or13_set_num_threads.argtypes = [ctypes.c_int]
         L.or13_fourier.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(Params), ctypes.c_int,
                                    ctypes.c_int, dp]
         _lib = L
@@ -220,3 +221,8 @@ def fourier(f: np.ndarray, p: Params, kx: int, ky: int) -> dict:
 
 def num_threads() -> int:
     return int(lib().or13_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timing only: results do not depend on it)."""
+    lib().or13_set_num_threads(int(n))

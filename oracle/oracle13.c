@@ -581,3 +581,14 @@ int or13_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the OpenMP loops from now on (n > 0); each node's update is
+ * independent, so results do not depend on it. */
+void or13_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
