@@ -96,3 +96,26 @@ def test_c_api_example_builds_without_torch(tmp_path):
     from paper_1401_0188_amd import build
     out = build.build_example(out=str(tmp_path / "c_api_example"))
     assert os.path.getsize(out) > 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every entry point raises: there is no CPU path."""
+    monkeypatch.setattr(lbm13, "LIB_PATH", str(tmp_path / "liblbm13.so"))
+    monkeypatch.setattr(lbm13, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        lbm13.lib()
+    with pytest.raises(Exception):
+        lbm13.Lattice(8, 8, lbm13.FP64)
+    with pytest.raises(Exception):
+        lbm13.Batch([(8, 8)], lbm13.FP32_DEV)
+
+
+def test_no_device_fails_loudly():
+    """On a host without a GPU the binding raises instead of computing on the CPU."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(Exception):
+        lbm13.Lattice(8, 8, lbm13.FP64)
+    with pytest.raises(Exception):
+        lbm13.Batch([(8, 8), (5, 3)], lbm13.FP32_DEV)
