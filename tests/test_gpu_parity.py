@@ -159,27 +159,64 @@ def test_streaming_only_is_bit_exact(precision, shape, kinds):
 
 # --------------------------------------------------------------------------- FP32 deviation form
 
+_CAVITY_ORACLE = {}
+
+
+def _cavity_256(Ra):
+    """The 256^2 heated cavity at Rayleigh number Ra (sec. 10 geometry: hot West,
+    cold East, adiabatic South and North walls, Pr = 0.71) and its oracle run of
+    10^4 steps, computed once per Ra."""
+    if Ra not in _CAVITY_ORACLE:
+        n, Pr, s_XX = 256, 0.71, 1.7
+        st, d = oracle.derive(oracle.params(Pr=Pr, s_XX=s_XX))
+        cf = workloads.cavity_forcing(n, Ra, Pr, d["nu"], d["kappa"])
+        dT = cf["dT"]
+        fields = workloads.cavity_fields(n, seed=0, dT=dT)
+        T_w = (-2 + dT / 2, -2 - dT / 2, 0, 0)
+        kw = dict(Pr=Pr, s_XX=s_XX, g=(0.0, -cf["g"]))
+        po, _ = params_pair(**dict(kw))
+        so = oracle.sides((2, 2, 1, 1), (0, 0, 0, 0), T_w)
+        f = oracle.run(oracle.init(*fields, po), po, so, 10000)
+        _CAVITY_ORACLE[Ra] = dict(n=n, cf=cf, fields=fields, T_w=T_w, kw=kw, f=f, po=po, so=so)
+    return _CAVITY_ORACLE[Ra]
+
+
 @pytest.mark.timeout(900)
-def test_fp32_cavity_256_1e4_steps():
-    """Heated cavity of 256^2 (sec. 10 geometry) at Ra = 1e5, Pr = 0.71, 10^4 steps:
-    FP32 deviation form within 1e-5 of the FP64 oracle on rho, u, T."""
+@pytest.mark.parametrize("spl", [1, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("Ra", [1e3, 1e4, 1e5])
+def test_cavity_256_1e4_steps(Ra, precision, spl):
+    """Heated cavity of 256^2 at Ra = 1e3, 1e4, 1e5, 10^4 steps, one and three
+    steps per launch: FP64 within 1e-12 of the oracle, the FP32 deviation form
+    within 1e-5 on rho, u, T; the mean Nusselt number and max |u| agree."""
     lbm13 = _lb()
-    n, Ra, Pr, s_XX = 256, 1e5, 0.71, 1.7
-    st, d = oracle.derive(oracle.params(Pr=Pr, s_XX=s_XX))
-    cf = workloads.cavity_forcing(n, Ra, Pr, d["nu"], d["kappa"])
-    dT = cf["dT"]
-    say("fp32 cavity 256^2 Ra=%g dT=%g g=%g, 10^4 steps" % (cf["Ra"], dT, cf["g"]))
-    fields = workloads.cavity_fields(n, seed=0, dT=dT)
-    T_w = (-2 + dT / 2, -2 - dT / 2, 0, 0)
-    lat, gs, gm, fs, om, f, po, so = run_both(n, n, fields, 10000, (2, 2, 1, 1), (0, 0, 0, 0), T_w,
-                                              precision=lbm13.FP32_DEV, Pr=Pr, s_XX=s_XX, g=(0.0, -cf["g"]))
+    c = _cavity_256(Ra)
+    n, cf = c["n"], c["cf"]
+    say("cavity 256^2 Ra=%g dT=%g g=%g precision %d, %d steps per launch, 10^4 steps"
+        % (cf["Ra"], cf["dT"], cf["g"], precision, spl))
+    _, pl = params_pair(**dict(c["kw"]))
+    lat = lbm13.Lattice(n, n, precision)
+    lat.set_steps_per_launch(spl)
+    lat.use_graph(120)
+    lat.set_params(sides=lbm13.make_sides((2, 2, 1, 1), (0, 0, 0, 0), c["T_w"]), **pl)
+    lat.init_moments(*c["fields"])
+    lat.step(10000)
+    gm = [t.cpu().numpy() for t in lat.moments()]
+    f, po, so = c["f"], c["po"], c["so"]
+    om = oracle.moments(f, po)
     assert np.isfinite(om[0]).all()
-    errs = assert_fp32(gm, om)
-    say("fp32 cavity errors rho %.2e ux %.2e uy %.2e T %.2e, u_max %.3e" % (*errs, np.abs(om[2]).max()))
+    if precision == 0:
+        assert_fp64(lat.get_state().cpu().numpy(), gm, oracle.collide(f, po), om)
+    else:
+        errs = assert_fp32(gm, om)
+        say("fp32 cavity errors rho %.2e ux %.2e uy %.2e T %.2e" % tuple(errs))
     od = oracle.diagnostics(f, po, so)
     gd = lat.diagnostics()
-    assert gd["Nu_mean"] == pytest.approx(od["Nu_mean"], rel=1e-4)
-    assert od["u_max"] > 1e-3  # convection has started
+    assert gd["Nu_mean"] == pytest.approx(od["Nu_mean"], rel=1e-10 if precision == 0 else 1e-4)
+    assert gd["u_max"] == pytest.approx(od["u_max"], rel=1e-10 if precision == 0 else 1e-3, abs=0 if precision == 0 else 1e-6)
+    if Ra >= 1e5:
+        assert od["u_max"] > 1e-3  # convection has started
+    lat.destroy()
 
 
 def test_fp32_shear_wave_matches_oracle():
