@@ -687,6 +687,57 @@ def test_channel_profiles_match_startup_series():
         assert np.abs(T - Tref).max() <= 0.03 * dT + heat, (kind, W, np.abs(T - Tref).max())
 
 
+@pytest.mark.timeout(900)
+def test_benchmark_channels_50000_steps():
+    """The 128 channels of the benchmark (W 32-256 with temperature walls, L
+    256-2048 periodic, half Couette, half Poiseuille; started from rest) in the
+    benchmark's three-step launch for 5 x 10^4 steps.  A channel stays uniform
+    along y, so each of its rows equals the oracle's run on a periodic strip of
+    4 rows with the same width and parameters: every ninth channel is compared
+    with that run at the FP32 bar (rho, u, T), every channel is checked to be
+    uniform along y, and u_y of every channel follows the start-up series within
+    3 % of its centreline speed (the scheme's own deviation, O(u_max^2): 2.5 % at
+    u_max = 0.05 in the oracle, 0.05 % at 0.005)."""
+    import bench
+    lbm13 = _lb()
+    specs = bench.channel_specs()
+    b = lbm13.Batch([(s["nx"], s["ny"]) for s in specs], lbm13.FP32_DEV)
+    ders = []
+    for i, s in enumerate(specs):
+        ders.append(b.set_params(i, sides=lbm13.make_sides(*s["sides"]), **s["kw"]))
+        b.init_moments(i, *bench.spec_fields(s))
+    b.set_fused_tile(32, 16)
+    b.set_interior_kernel(False)
+    b.set_steps_per_launch(3)
+    b.use_graph(120)
+    steps = 50000
+    say("128 benchmark channels, %d steps" % steps)
+    b.step(steps)
+    for i, s in enumerate(specs):
+        W, L = s["nx"], s["ny"]
+        m = [t.cpu().numpy() for t in b.moments(i)]
+        row = [q[L // 2] for q in m]
+        for k, q in enumerate(m):
+            assert np.abs(q - row[k]).max() <= 1e-6 * max(1.0, np.abs(row[k]).max()), (i, k)
+        xi = np.arange(W) + 0.5
+        nu = ders[i]["nu"]
+        if s["info"]["kind"] == "couette":
+            U = s["sides"][1][0]
+            ref, scale = startup_couette(xi, W, U, nu, steps), U
+        else:
+            F = s["kw"]["F0"][1]
+            ref, scale = startup_poiseuille(xi, W, F, nu, steps), F * W * W / (8 * nu)
+        assert np.abs(row[2] - ref).max() <= 0.03 * scale, (i, s["info"]["kind"], W, np.abs(row[2] - ref).max() / scale)
+        if i % 9 == 0:
+            say("channel %d (%s, W %d) against the oracle on a 4-row strip" % (i, s["info"]["kind"], W))
+            po, _ = params_pair(**dict(s["kw"]))
+            f = oracle.run(oracle.init(*workloads.rest_fields(W, 4, s["kw"]["E0"]), po), po,
+                           oracle.sides(*s["sides"]), steps)
+            om = oracle.moments(f, po)
+            assert_fp32([q[None, :] for q in row], [q[2:3] for q in om])
+    b.destroy()
+
+
 # --------------------------------------------------------------------------- two steps per launch
 
 @pytest.mark.parametrize("name", sorted(WALL_CASES))
