@@ -517,97 +517,142 @@ def main_batched(args, copy_gbps):
     }
 
 
-def small_case(workload):
+CAVITY_RA = (1e3, 1e4, 1e5)
+
+
+def small_cases(workload):
     """The small configurations, whose state fits in the caches: the 32^2
-    periodic wave in FP64 (1000 steps) and the 256^2 heated cavity at Ra = 1e5,
-    Pr = 0.71 in FP64 and FP32 (10^4 steps)."""
+    periodic wave in FP64 (1000 steps, checked against the oracle over the
+    whole run) and the 256^2 heated cavity at Ra = 1e3, 1e4, 1e5, Pr = 0.71 in
+    FP64 and FP32 (10^5 steps timed; the error against the oracle after 10^4
+    steps, the horizon of the stated bounds)."""
     from paper_1401_0188_amd import workloads
     if workload == "wave32":
-        return dict(n=32, steps=1000, forms=(0,), fields=workloads.periodic_wave(32), kinds=(0, 0, 0, 0),
-                    T_w=(0, 0, 0, 0), kw={}, desc="periodic 32x32 nonlinear wave (rho, ux cosine)")
+        return [dict(n=32, steps=1000, check_steps=1000, forms=(0,), fields=workloads.periodic_wave(32),
+                     kinds=(0, 0, 0, 0), T_w=(0, 0, 0, 0), kw={}, label="wave",
+                     desc="periodic 32x32 nonlinear wave (rho, ux cosine)")]
     from paper_1401_0188_amd import lbm13
-    n, Ra, Pr, s_XX = 256, 1e5, 0.71, 1.7
+    n, Pr, s_XX = 256, 0.71, 1.7
     st, d = lbm13.derive(Pr=Pr, s_XX=s_XX)
-    cf = workloads.cavity_forcing(n, Ra, Pr, d["nu"], d["kappa"])
-    return dict(n=n, steps=10000, forms=(0, 1), fields=workloads.cavity_fields(n, seed=0, dT=cf["dT"]),
-                kinds=(2, 2, 1, 1), T_w=(-2 + cf["dT"] / 2, -2 - cf["dT"] / 2, 0, 0),
-                kw=dict(Pr=Pr, s_XX=s_XX, g=(0.0, -cf["g"])),
-                desc="heated cavity 256x256, Ra %.3g (dT %.3g), Pr 0.71, hot West / cold East, adiabatic S/N" % (
-                    cf["Ra"], cf["dT"]))
+    out = []
+    for Ra in CAVITY_RA:
+        cf = workloads.cavity_forcing(n, Ra, Pr, d["nu"], d["kappa"])
+        out.append(dict(n=n, steps=100000, check_steps=10000, forms=(0, 1),
+                        fields=workloads.cavity_fields(n, seed=0, dT=cf["dT"]), kinds=(2, 2, 1, 1),
+                        T_w=(-2 + cf["dT"] / 2, -2 - cf["dT"] / 2, 0, 0),
+                        kw=dict(Pr=Pr, s_XX=s_XX, g=(0.0, -cf["g"])), label="Ra %.0e" % Ra,
+                        Ra=cf["Ra"], dT=cf["dT"], g=cf["g"],
+                        desc="heated cavity 256x256, Ra 1e3, 1e4, 1e5, Pr 0.71, hot West / cold East, adiabatic S/N"))
+    return out
 
 
-def cpu_baseline_small(c):
-    """The FP64 CPU oracle over a whole small configuration: its rate, and its
-    moments after the configuration's steps (the reference of the error)."""
+def cpu_baseline_small(cases):
+    """The FP64 CPU oracle over each small case's checked steps: its rate, and
+    its moments after them (the reference of the error)."""
     import oracle
-    kw = dict(c["kw"])
-    g = kw.pop("g", (0.0, 0.0))
-    po = oracle.params(gx=g[0], gy=g[1], **kw)
-    so = oracle.sides(c["kinds"], (0, 0, 0, 0), c["T_w"])
-    t0 = time.perf_counter()
-    f = oracle.run(oracle.init(*c["fields"], po), po, so, c["steps"])
-    el = time.perf_counter() - t0
-    om = oracle.moments(f, po)
-    rec = dict(value=round(c["n"] * c["n"] * c["steps"] / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(),
-               kind="oracle", sample="the whole run, %d steps, %.1f s" % (c["steps"], el))
+    oms, upd, el = [], 0, 0.0
+    for c in cases:
+        kw = dict(c["kw"])
+        g = kw.pop("g", (0.0, 0.0))
+        po = oracle.params(gx=g[0], gy=g[1], **kw)
+        so = oracle.sides(c["kinds"], (0, 0, 0, 0), c["T_w"])
+        t0 = time.perf_counter()
+        f = oracle.run(oracle.init(*c["fields"], po), po, so, c["check_steps"])
+        el += time.perf_counter() - t0
+        upd += c["n"] * c["n"] * c["check_steps"]
+        oms.append(oracle.moments(f, po))
+    rec = dict(value=round(upd / el / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+               sample="%d steps of each of %d case(s) (%s), %.1f s" % (
+                   cases[0]["check_steps"], len(cases), ", ".join(c["label"] for c in cases), el))
     state = [f]
 
     def advance():
         state[0] = oracle.step(state[0], po, so)
-    one_thread(rec, advance, c["n"] * c["n"], min(3.0, max(el, 0.05)))
-    return rec, om
+    one_thread(rec, advance, cases[-1]["n"] ** 2, min(3.0, max(el / len(cases), 0.05)))
+    return rec, oms
 
 
 def main_small(args, copy_gbps):
-    """A small configuration: each form timed over the configuration's steps
-    (autotuned launch), its error against the oracle after the same steps, and
-    the oracle's own rate on the host."""
+    """A small configuration: each form of each case timed over the case's
+    steps (autotuned launch), its error against the oracle after the checked
+    steps, the FP64 diagnostics (Nusselt numbers, centro-asymmetry) at the end,
+    FP32 against FP64 after the whole run, and the oracle's own rate."""
     import torch
 
     from paper_1401_0188_amd import lbm13
-    c = small_case(args.workload)
-    n, steps = c["n"], c["steps"]
-    log("%s: oracle, %d steps" % (args.workload, steps))
-    cpu, om = cpu_baseline_small(c)
-    forms = {}
-    for prec in c["forms"]:
-        lat = lbm13.Lattice(n, n, prec)
-        lat.set_params(sides=lbm13.make_sides(c["kinds"], (0, 0, 0, 0), c["T_w"]), **c["kw"])
-        lat.init_moments(*c["fields"])
-        lat.autotune(12)
-        lat.init_moments(*c["fields"])
-        launch = lat.launch_config()
-        if not args.no_graph:
-            lat.use_graph(GRAPH_K)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        t1 = time.perf_counter()
-        a.record(lat.stream)
-        lat.step(steps)
-        b.record(lat.stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t1
-        gm = [t.cpu().numpy() for t in lat.moments()]
-        forms["fp64" if prec == 0 else "fp32"] = {
-            "value": round(n * n * steps / wall / 1e6, 1), "unit": "MLUPS",
-            "kernel_ms_per_step": round(a.elapsed_time(b) / steps, 5), "launch": launch,
-            "error_vs_oracle": moment_errors(gm, om)}
-        lat.destroy()
-        del lat
-        torch.cuda.empty_cache()
-    head = forms["fp32"] if "fp32" in forms else forms["fp64"]
+    cases = small_cases(args.workload)
+    log("%s: oracle, %d case(s)" % (args.workload, len(cases)))
+    cpu, oms = cpu_baseline_small(cases)
+    out, tot = [], {}
+    for c, om in zip(cases, oms):
+        n, steps = c["n"], c["steps"]
+        rec = {"case": c["label"]}
+        rec.update({k: round(c[k], 6) for k in ("Ra", "dT", "g") if k in c})
+        finals = {}
+        for prec in c["forms"]:
+            name = "fp64" if prec == 0 else "fp32"
+            log("%s %s: %d steps" % (c["label"], name, steps))
+            lat = lbm13.Lattice(n, n, prec)
+            lat.set_params(sides=lbm13.make_sides(c["kinds"], (0, 0, 0, 0), c["T_w"]), **c["kw"])
+            lat.init_moments(*c["fields"])
+            lat.autotune(12)
+            launch = lat.launch_config()
+            if not args.no_graph:
+                lat.use_graph(GRAPH_K)
+            if c["check_steps"] != steps:
+                lat.init_moments(*c["fields"])
+                lat.step(c["check_steps"])
+                err = moment_errors([t.cpu().numpy() for t in lat.moments()], om)
+            lat.init_moments(*c["fields"])
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            t1 = time.perf_counter()
+            a.record(lat.stream)
+            lat.step(steps)
+            b.record(lat.stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            gm = [t.cpu().numpy() for t in lat.moments()]
+            if c["check_steps"] == steps:
+                err = moment_errors(gm, om)
+            finals[prec] = gm
+            d = lat.diagnostics()
+            rec[name] = {"value": round(n * n * steps / wall / 1e6, 1), "unit": "MLUPS",
+                         "kernel_ms_per_step": round(a.elapsed_time(b) / steps, 5), "launch": launch,
+                         "error_vs_oracle": err}
+            if c["kinds"][0] != 0:
+                rec[name].update({k: round(float(d[k]), 6) for k in ("Nu_mean", "Nu_west", "Nu_east", "asym_rel",
+                                                                     "u_max")})
+            t = tot.setdefault(name, [0, 0.0])
+            t[0] += n * n * steps
+            t[1] += wall
+            lat.destroy()
+            del lat
+            torch.cuda.empty_cache()
+        if 0 in finals and 1 in finals:
+            rec["fp32_vs_fp64_gpu"] = moment_errors(finals[1], finals[0])
+        out.append(rec)
+    head = "fp32" if "fp32" in tot else "fp64"
+    value = tot[head][0] / tot[head][1] / 1e6
+    n, steps, check = cases[0]["n"], cases[0]["steps"], cases[0]["check_steps"]
+
+    def worst(errs):  # the largest error of each quantity over the cases
+        return {q: max(e[q] for e in errs) for q in ("rho_rel", "u_abs", "T_rel")}
+    error = {"bounds": {"fp64": 1e-12, "fp32": 1e-5},
+             "vs_oracle": {"steps": check, **{k: worst([r[k]["error_vs_oracle"] for r in out]) for k in tot}}}
+    if len(tot) == 2:
+        error["fp32_vs_fp64_gpu"] = {"steps": steps, **worst([r["fp32_vs_fp64_gpu"] for r in out])}
     return {
-        "metric": METRIC, "value": head["value"], "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": 0,
-        "ms_per_step": round(n * n / head["value"] / 1e3, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if "fp32" in forms else "f64", "data": "synthetic",
-        "config": {"workload": c["desc"], "nx": n, "ny": n, "steps": steps,
+        "metric": METRIC, "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(n * n / value / 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if head == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": cases[0]["desc"], "nx": n, "ny": n, "steps": steps, "cases": len(cases),
                    "note": "state resident in the L2 / MALL caches: no HBM roofline claim"},
         "roofline": None,
         "cpu_baseline": cpu,
-        "forms": forms,
-        "error": {"bounds": {"fp64": 1e-12, "fp32": 1e-5},
-                  "vs_oracle": {k: v["error_vs_oracle"] for k, v in forms.items()}, "steps": steps},
+        "cases": out,
+        "error": error,
         "copy_GBps": round(copy_gbps, 1),
         "kernel_source_sha": kernel_sha(),
     }
