@@ -492,6 +492,12 @@ def main_batched(args, copy_gbps):
                                  **per[worst], **specs[worst]["info"])}}
     clamped = sum(1 for s in specs if s["info"].get("clamped"))
     nonfinite = sum(1 for d in r32["diag"] if d["nonfinite"] > 0)
+    # FP64 diagnostics of every domain at the end of the timed run (min, median, max), after
+    # warm-up + timed steps from rest: early in a run these are start-up transients
+    summary = {"steps_from_start": args.warmup + args.steps}
+    for k in ("Nu_mean", "asym_rel", "u_max"):
+        v = sorted(float(d[k]) for d in r32["diag"])
+        summary[k] = {"min": round(v[0], 6), "median": round(v[len(v) // 2], 6), "max": round(v[-1], 6)}
     return {
         "metric": METRIC, "value": round(r32["mlups"], 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 5), "higher_is_better": True,
@@ -512,6 +518,7 @@ def main_batched(args, copy_gbps):
         "kernel_ms_per_launch": round(r32["kernel_ms_per_launch"], 5),
         "copy_GBps": round(copy_gbps, 1),
         "domains_nonfinite": nonfinite,
+        "diagnostics_at_end": summary,
         "error": err,
         "kernel_source_sha": kernel_sha(),
     }
@@ -604,6 +611,7 @@ def main_small(args, copy_gbps):
                 lat.step(c["check_steps"])
                 err = moment_errors([t.cpu().numpy() for t in lat.moments()], om)
             lat.init_moments(*c["fields"])
+            d0 = lat.diagnostics()
             torch.cuda.synchronize()
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
@@ -620,7 +628,9 @@ def main_small(args, copy_gbps):
             d = lat.diagnostics()
             rec[name] = {"value": round(n * n * steps / wall / 1e6, 1), "unit": "MLUPS",
                          "kernel_ms_per_step": round(a.elapsed_time(b) / steps, 5), "launch": launch,
-                         "error_vs_oracle": err}
+                         "error_vs_oracle": err,
+                         # change of the conserved sums over the run (FP64 reductions; a periodic box keeps them)
+                         "drift": {k: float(d[k] - d0[k]) for k in ("sum_rho", "sum_jx", "sum_jy", "sum_E")}}
             if c["kinds"][0] != 0:
                 rec[name].update({k: round(float(d[k]), 6) for k in ("Nu_mean", "Nu_west", "Nu_east", "asym_rel",
                                                                      "u_max")})
