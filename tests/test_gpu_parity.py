@@ -515,26 +515,67 @@ def test_graph_replay_is_bit_exact_with_direct_steps(spl, k, odd):
     a.set_steps_per_launch(spl)
     a.set_params(sides=sides, g=(0.0, -0.05))
     a.init_moments(*fields)
-    for _ in range(5):
-        a.step(k)
-    ref = a.get_state().cpu().numpy()
     b = lbm13.Lattice(128, 96, lbm13.FP32_DEV)
     b.set_steps_per_launch(spl)
     b.set_params(sides=sides, g=(0.0, -0.05))
     b.init_moments(*fields)
     b.use_graph(k)
-    for _ in range(5):
+    for rep in range(5):  # every replay against the direct launches, eager work in between
+        a.step(k)
         b.step(k)
         torch.cuda.synchronize()
-        _ = [t.sum().item() for t in b.moments()]  # eager work between replays
+        _ = [t.sum().item() for t in b.moments()]
+        b.diagnostics()
+        assert np.array_equal(b.get_state().cpu().numpy(), a.get_state().cpu().numpy()), rep
     assert b.steps_done() == 5 * k
-    assert np.array_equal(b.get_state().cpu().numpy(), ref)
     b.step(odd)  # one launch outside the graphs, then graphs of the other parity
     b.step(2 * k)
     a.step(odd)
     a.step(k)
     a.step(k)
     assert np.array_equal(b.get_state().cpu().numpy(), a.get_state().cpu().numpy())
+
+
+@pytest.mark.parametrize("interior", [True, False])
+def test_batched_graph_replays_match_direct_launches(interior):
+    """A batch in three-step launches captured in graphs (with the interior
+    kernel on, each launch forks onto a second stream and joins back inside
+    the graph): every replay against the same launches made directly, with
+    eager work (moments, diagnostics, host copies) between the replays."""
+    lbm13 = _lb()
+    import torch
+    cases = [(96, 64, (2, 2, 1, 1), (0, 0, 0.02, 0), (-1.99, -2.01, 0, 0), dict(g=(0.0, -1e-3))),
+             (160, 128, (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0), dict(F0=(1e-5, 0.0))),
+             (40, 200, (2, 2, 0, 0), (0.03, 0, 0, 0), (-1.99, -2.01, 0, 0), dict(F0=(0.0, 1e-6)))]
+    say("batched graph replays, interior kernel %s" % interior)
+
+    def make():
+        b = lbm13.Batch([(c[0], c[1]) for c in cases], lbm13.FP32_DEV)
+        b.set_fused_tile(32, 16)
+        b.set_interior_kernel(interior)
+        b.set_steps_per_launch(3)
+        for i, (nx, ny, kinds, u_t, T_w, kw) in enumerate(cases):
+            b.set_params(i, sides=lbm13.make_sides(kinds, u_t, T_w), **kw)
+            b.init_moments(i, *workloads.cavity_fields(nx, ny=ny, seed=60 + i, dT=0.01))
+        return b
+    a, b = make(), make()
+    b.use_graph(6)
+    for rep in range(5):
+        a.step(6)
+        b.step(6)
+        torch.cuda.synchronize()
+        _ = [t.sum().item() for t in b.moments(rep % len(cases))]
+        b.diagnostics()
+        for i in range(len(cases)):
+            assert np.array_equal(b.get_state(i).cpu().numpy(), a.get_state(i).cpu().numpy()), (rep, i)
+    b.step(4)  # a remainder outside the graphs, then graphs again
+    b.step(12)
+    a.step(4)
+    a.step(12)
+    for i in range(len(cases)):
+        assert np.array_equal(b.get_state(i).cpu().numpy(), a.get_state(i).cpu().numpy()), i
+    a.destroy()
+    b.destroy()
 
 
 @pytest.mark.parametrize("spl", [1, 3])
