@@ -199,6 +199,30 @@ class _Base:
     def set_interior_kernel(self, on: bool):
         self._check(getattr(lib(), self._prefix + "set_interior_kernel")(self._h, int(bool(on))))
 
+    # The library works on the context's stream; tensors cross between it and
+    # the caller's current stream here.  Both helpers do nothing when the two
+    # streams are the same (the default).
+    def _use(self, tensors):
+        """Tensors the library reads or writes on the context's stream: that
+        stream first waits for the work queued on the caller's stream (the
+        tensors' contents, or earlier uses of their memory), and the allocator
+        keeps their memory until the context's stream is done with it."""
+        torch = _torch()
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+            for t in tensors:
+                t.record_stream(self.stream)
+
+    def _hand_over(self, tensors):
+        """Tensors the library wrote on the context's stream, returned to the
+        caller: the caller's stream waits for them."""
+        torch = _torch()
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+        return tensors
+
     def _check(self, st):
         if st != OK:
             msg = getattr(lib(), self._prefix + "last_error")(self._h)
@@ -220,6 +244,7 @@ class Lattice(_Base):
             raise LBM13Error(EINVAL, "invalid size or precision")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._use([self.workspace])
         h = ctypes.c_void_p()
         st = L.lbm13_create(self.nx, self.ny, self.precision, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
@@ -241,6 +266,7 @@ class Lattice(_Base):
         n = self.nx * self.ny
         f = [_dev_f64(a, torch, n) for a in (rho, ux, uy, T)]
         self._keep = f  # kept alive until the next init (the kernel is async)
+        self._use(f)
         self._check(lib().lbm13_init_moments(self._h, *[ctypes.c_void_p(t.data_ptr()) for t in f]))
 
     def step(self, n: int = 1):
@@ -249,8 +275,9 @@ class Lattice(_Base):
     def moments(self):
         torch = _torch()
         out = [torch.empty((self.ny, self.nx), dtype=torch.float64, device="cuda") for _ in range(4)]
+        self._use(out)
         self._check(lib().lbm13_moments(self._h, *[ctypes.c_void_p(t.data_ptr()) for t in out]))
-        return tuple(out)
+        return tuple(self._hand_over(out))
 
     def diagnostics(self, check: bool = True):
         out = (ctypes.c_double * 16)()
@@ -268,24 +295,28 @@ class Lattice(_Base):
     def get_state(self):
         torch = _torch()
         out = torch.empty((13, self.ny, self.nx), dtype=torch.float64, device="cuda")
+        self._use([out])
         self._check(lib().lbm13_get_state(self._h, ctypes.c_void_p(out.data_ptr())))
-        return out
+        return self._hand_over([out])[0]
 
     def set_state(self, src):
         torch = _torch()
         t = _dev_f64(src, torch, 13 * self.nx * self.ny)
         self._keep = [t]
+        self._use([t])
         self._check(lib().lbm13_set_state(self._h, ctypes.c_void_p(t.data_ptr())))
 
     def save(self):
         """Raw checkpoint (device uint8 tensor) of the stored working-precision state."""
         torch = _torch()
         out = torch.empty(int(lib().lbm13_state_bytes(self._h)), dtype=torch.uint8, device="cuda")
+        self._use([out])
         self._check(lib().lbm13_save(self._h, ctypes.c_void_p(out.data_ptr())))
-        return out
+        return self._hand_over([out])[0]
 
     def load(self, blob):
         self._keep = [blob]
+        self._use([blob])
         self._check(lib().lbm13_load(self._h, ctypes.c_void_p(blob.data_ptr())))
 
     def steps_done(self) -> int:
@@ -338,6 +369,7 @@ class Batch(_Base):
             raise LBM13Error(EINVAL, "invalid sizes or precision")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._use([self.workspace])
         h = ctypes.c_void_p()
         st = L.lbm13_batch_create(self.count, nx, ny, self.precision, ctypes.c_void_p(self.workspace.data_ptr()),
                                   nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
@@ -359,6 +391,7 @@ class Batch(_Base):
         nx, ny = self.sizes[i]
         f = [_dev_f64(a, torch, nx * ny) for a in (rho, ux, uy, T)]
         self._keep[i] = f
+        self._use(f)
         self._check(lib().lbm13_batch_init_moments(self._h, int(i), *[ctypes.c_void_p(t.data_ptr()) for t in f]))
 
     def step(self, n: int = 1):
@@ -368,8 +401,9 @@ class Batch(_Base):
         torch = _torch()
         nx, ny = self.sizes[i]
         out = [torch.empty((ny, nx), dtype=torch.float64, device="cuda") for _ in range(4)]
+        self._use(out)
         self._check(lib().lbm13_batch_moments(self._h, int(i), *[ctypes.c_void_p(t.data_ptr()) for t in out]))
-        return tuple(out)
+        return tuple(self._hand_over(out))
 
     def diagnostics(self, check: bool = True):
         out = (ctypes.c_double * (16 * self.count))()
@@ -388,24 +422,28 @@ class Batch(_Base):
         torch = _torch()
         nx, ny = self.sizes[i]
         out = torch.empty((13, ny, nx), dtype=torch.float64, device="cuda")
+        self._use([out])
         self._check(lib().lbm13_batch_get_state(self._h, int(i), ctypes.c_void_p(out.data_ptr())))
-        return out
+        return self._hand_over([out])[0]
 
     def set_state(self, i: int, src):
         torch = _torch()
         nx, ny = self.sizes[i]
         t = _dev_f64(src, torch, 13 * nx * ny)
         self._keep[("state", i)] = t
+        self._use([t])
         self._check(lib().lbm13_batch_set_state(self._h, int(i), ctypes.c_void_p(t.data_ptr())))
 
     def save(self, i: int):
         torch = _torch()
         out = torch.empty(int(lib().lbm13_batch_state_bytes(self._h, int(i))), dtype=torch.uint8, device="cuda")
+        self._use([out])
         self._check(lib().lbm13_batch_save(self._h, int(i), ctypes.c_void_p(out.data_ptr())))
-        return out
+        return self._hand_over([out])[0]
 
     def load(self, i: int, blob):
         self._keep[("blob", i)] = blob
+        self._use([blob])
         self._check(lib().lbm13_batch_load(self._h, int(i), ctypes.c_void_p(blob.data_ptr())))
 
     def set_tile(self, tile_x: int, tile_y: int):

@@ -536,6 +536,51 @@ def test_graph_replay_is_bit_exact_with_direct_steps(spl, k, odd):
     assert np.array_equal(b.get_state().cpu().numpy(), a.get_state().cpu().numpy())
 
 
+def test_contexts_on_separate_streams_are_independent():
+    """Two contexts on two streams other than the caller's, their three-step
+    launches (each forking onto its own auxiliary stream and joining back)
+    interleaved, one of them replayed from graphs: each equals, bit for bit, the
+    same context run alone; the fields they hand back are complete when the
+    caller's stream reads them."""
+    lbm13 = _lb()
+    import torch
+    cfgs = [(160, 128, (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0), dict(F0=(1e-5, 0.0)), 0),
+            (96, 64, (2, 2, 1, 1), (0, 0, 0.02, 0), (-1.99, -2.01, 0, 0), dict(g=(0.0, -1e-3)), 6)]
+    say("two contexts on two streams")
+
+    def make(stream, c):
+        nx, ny, kinds, u_t, T_w, kw, graph = c
+        lat = lbm13.Lattice(nx, ny, lbm13.FP32_DEV, stream=stream)
+        lat.set_fused_tile(32, 16)
+        lat.set_steps_per_launch(3)
+        lat.set_params(sides=lbm13.make_sides(kinds, u_t, T_w), **kw)
+        lat.init_moments(*workloads.cavity_fields(nx, ny=ny, seed=70, dT=0.01))
+        if graph:
+            lat.use_graph(graph)
+        return lat
+    solo = []
+    for c in cfgs:
+        lat = make(torch.cuda.current_stream(), c)
+        lat.step(30)
+        torch.cuda.synchronize()
+        solo.append(lat.get_state().cpu().numpy())
+        lat.destroy()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a, b = make(s1, cfgs[0]), make(s2, cfgs[1])
+    for _ in range(5):
+        a.step(6)
+        b.step(6)
+    # no device-wide synchronisation: the binding orders the caller's stream after
+    # the context's stream for the tensors it returns
+    assert np.array_equal(a.get_state().cpu().numpy(), solo[0])
+    assert np.array_equal(b.get_state().cpu().numpy(), solo[1])
+    ma = [t.sum().item() for t in a.moments()]
+    torch.cuda.synchronize()
+    assert ma == [t.sum().item() for t in a.moments()]
+    a.destroy()
+    b.destroy()
+
+
 @pytest.mark.parametrize("interior", [True, False])
 def test_batched_graph_replays_match_direct_launches(interior):
     """A batch in three-step launches captured in graphs (with the interior
