@@ -244,7 +244,9 @@ int lbm13_set_fused_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
  * the same arithmetic differently).  EINVAL otherwise. */
 int lbm13_set_interior_kernel(lbm13_ctx *ctx, int on);
 
-/* Destroy the context (frees host objects and graphs; never the workspace). */
+/* Destroy the context: waits for the work queued on its stream (graph
+ * replays included), then frees its host objects, graphs, auxiliary streams and
+ * events; never the workspace, which the caller may free once this returns. */
 int lbm13_destroy(lbm13_ctx *ctx);
 
 /* Message of the last failing call on ctx ("" if none; a static message when

@@ -1055,6 +1055,10 @@ long long lbm13_batch_nodes(const lbm13_batch* b) {
 
 int lbm13_batch_destroy(lbm13_batch* b) {
     if (!b) return LBM13_EINVAL;
+    // queued launches and graph replays still use the graphs, streams, events
+    // and workspace: let them finish first
+    (void)hipStreamSynchronize(b->stream);
+    if (b->aux) (void)hipStreamSynchronize(b->aux);
     drop_graphs(b);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     if (b->aux) (void)hipStreamDestroy(b->aux);

@@ -536,6 +536,33 @@ def test_graph_replay_is_bit_exact_with_direct_steps(spl, k, odd):
     assert np.array_equal(b.get_state().cpu().numpy(), a.get_state().cpu().numpy())
 
 
+def test_destroy_waits_for_queued_work():
+    """lbm13_destroy right after queueing graph replays and three-step launches
+    (no synchronisation): it waits for them before releasing graphs, streams and
+    events, so freeing the workspace afterwards is safe and the device is left
+    without errors for the next context."""
+    lbm13 = _lb()
+    import torch
+    say("destroy with queued work")
+    fields = workloads.cavity_fields(256, ny=192, seed=80, dT=0.01)
+    for graph in (0, 120):
+        lat = lbm13.Lattice(256, 192, lbm13.FP32_DEV)
+        lat.set_steps_per_launch(3)
+        lat.set_params(sides=lbm13.make_sides((2, 2, 1, 1), (0, 0, 0, 0), (-1.99, -2.01, 0, 0)), g=(0.0, -1e-3))
+        lat.init_moments(*fields)
+        if graph:
+            lat.use_graph(graph)
+        lat.step(1200)
+        lat.destroy()
+        del lat
+        torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+    lat, gs, gm, fs, om, *_ = run_both(64, 48, workloads.cavity_fields(64, ny=48, seed=81), 30, (2, 2, 1, 1),
+                                       (0, 0, 0, 0), (-1.99, -2.01, 0, 0), precision=0, spl=3, g=(0.0, -1e-3))
+    assert_fp64(gs, gm, fs, om)
+    lat.destroy()
+
+
 def test_contexts_on_separate_streams_are_independent():
     """Two contexts on two streams other than the caller's, their three-step
     launches (each forking onto its own auxiliary stream and joining back)
