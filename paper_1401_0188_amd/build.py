@@ -51,7 +51,8 @@ def build_example(out: str = EXAMPLE, verbose: bool = False) -> str:
     """Compile the standalone C-ABI example against the built library (no
     PyTorch): hipMalloc'd workspace, the library's calls, a decay check."""
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17", "-I" + os.path.join(ROOT, "include"), EXAMPLE_SRC,
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-I" + os.path.join(ROOT, "include"), EXAMPLE_SRC,
            "-L" + HERE, "-llbm13", "-Wl,-rpath," + HERE, "-Wl,-rpath,$ORIGIN/..", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
