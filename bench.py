@@ -693,7 +693,7 @@ def main():
                     help="fix the FP64 launch configuration (as --launch-fp32)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(a domain would shard as y-slabs exchanging 2-row halos)", file=sys.stderr)
         sys.exit(2)
 
