@@ -219,11 +219,29 @@ def test_cavity_256_1e4_steps(Ra, precision, spl):
     lat.destroy()
 
 
-def test_fp32_shear_wave_matches_oracle():
+_WAVE_ORACLE = {}
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("spl", [1, 3])
+def test_fp32_shear_wave_matches_oracle(spl):
+    """The shear + acoustic wave of the 4096^2 benchmark at 256^2, 10^4 steps, one
+    and three steps per launch: FP32 deviation form within 1e-5 of the oracle."""
     lbm13 = _lb()
-    say("fp32 shear+acoustic 256x256, 2000 steps")
-    lat, gs, gm, fs, om, *_ = run_both(256, 256, workloads.shear_acoustic(256), 2000, precision=lbm13.FP32_DEV)
-    assert_fp32(gm, om)
+    n, steps = 256, 10000
+    say("fp32 shear+acoustic %dx%d, %d steps, %d steps per launch" % (n, n, steps, spl))
+    fields = workloads.shear_acoustic(n)
+    if n not in _WAVE_ORACLE:
+        po = oracle.params()
+        _WAVE_ORACLE[n] = oracle.moments(oracle.run(oracle.init(*fields, po), po, oracle.sides(), steps), po)
+    lat = lbm13.Lattice(n, n, lbm13.FP32_DEV)
+    lat.set_steps_per_launch(spl)
+    lat.use_graph(120)
+    lat.set_params()
+    lat.init_moments(*fields)
+    lat.step(steps)
+    assert_fp32([t.cpu().numpy() for t in lat.moments()], _WAVE_ORACLE[n])
+    lat.destroy()
 
 
 # --------------------------------------------------------------------------- full size 4096^2
