@@ -554,6 +554,57 @@ def test_graph_replay_is_bit_exact_with_direct_steps(spl, k, odd):
     assert np.array_equal(b.get_state().cpu().numpy(), a.get_state().cpu().numpy())
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_node_written_and_runs_deterministic(precision):
+    """The workspace starts as all-ones bytes (NaN in both precisions) before the
+    context is created on it, so a node that a launch leaves unwritten would
+    surface as NaN: one launch of one, two and three steps from the initial
+    state (which writes the other buffer once, fully) on walled, periodic and
+    ragged domains must give finite states equal to the oracle's; a second run
+    of the same case is bitwise identical."""
+    import ctypes
+    import torch
+    lbm13 = _lb()
+    L = lbm13.lib()
+    cases = [(67, 45, (2, 2, 1, 1), (0, 0, 0.02, 0), (-1.99, -2.01, 0, 0), dict(g=(0.0, -1e-3))),
+             (203, 93, (0, 0, 0, 0), (0, 0, 0, 0), (0, 0, 0, 0), dict(F0=(1e-5, 0.0))),
+             (150, 37, (0, 0, 2, 2), (0, 0, 0.01, -0.01), (0, 0, -1.99, -2.01), dict())]
+
+    def run(nx, ny, kinds, u_t, T_w, kw, spl, fields):
+        nbytes = L.lbm13_workspace_bytes(nx, ny, precision)
+        ws = torch.full((nbytes,), 255, dtype=torch.uint8, device="cuda")
+        stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        assert L.lbm13_create(nx, ny, precision, ctypes.c_void_p(ws.data_ptr()), nbytes,
+                              ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)) == lbm13.OK
+        d = lbm13.Derived()
+        assert L.lbm13_set_params(h, ctypes.byref(lbm13.make_params(**kw)), lbm13.make_sides(kinds, u_t, T_w),
+                                  ctypes.byref(d)) == lbm13.OK
+        assert L.lbm13_set_steps_per_launch(h, spl) == lbm13.OK
+        dev = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda") for a in fields]
+        assert L.lbm13_init_moments(h, *[ctypes.c_void_p(t.data_ptr()) for t in dev]) == lbm13.OK
+        assert L.lbm13_step(h, spl) == lbm13.OK
+        out = torch.empty((13, ny, nx), dtype=torch.float64, device="cuda")
+        assert L.lbm13_get_state(h, ctypes.c_void_p(out.data_ptr())) == lbm13.OK
+        torch.cuda.synchronize()
+        assert L.lbm13_destroy(h) == lbm13.OK
+        return out.cpu().numpy()
+
+    for nx, ny, kinds, u_t, T_w, kw in cases:
+        fields = workloads.cavity_fields(nx, ny=ny, seed=90, dT=0.01)
+        po, _ = params_pair(**dict(kw))
+        so = oracle.sides(kinds, u_t, T_w)
+        for spl in (1, 2, 3):
+            say("poisoned workspace %d x %d sides %s, one launch of %d steps, precision %d"
+                % (nx, ny, kinds, spl, precision))
+            g1 = run(nx, ny, kinds, u_t, T_w, kw, spl, fields)
+            assert np.isfinite(g1).all()
+            fs = oracle.collide(oracle.run(oracle.init(*fields, po), po, so, spl), po)
+            tol = 1e-12 if precision == 0 else 1e-5
+            assert np.abs(g1 - fs).max() <= tol * np.abs(fs).max()
+            assert np.array_equal(g1, run(nx, ny, kinds, u_t, T_w, kw, spl, fields))
+
+
 def test_destroy_waits_for_queued_work():
     """lbm13_destroy right after queueing graph replays and three-step launches
     (no synchronisation): it waits for them before releasing graphs, streams and
