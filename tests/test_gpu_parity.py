@@ -308,6 +308,21 @@ def test_maximum_sizes(nx, ny, axis, precision, spl):
     lat.destroy()
 
 
+def test_readme_python_example_runs():
+    """The Python usage block of README.md, run as written: the documented calls
+    exist and a heated cavity advances to a finite Nusselt number."""
+    import contextlib
+    import io
+    import re
+    say("README example")
+    text = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "README.md")).read()
+    block = re.search(r"## Use \(Python\)\s*```python\n(.*?)```", text, re.S).group(1)
+    out = io.StringIO()
+    with contextlib.redirect_stdout(out):
+        exec(compile(block, "README.md", "exec"), {})
+    assert np.isfinite(float(out.getvalue().strip().splitlines()[-1]))
+
+
 def test_c_api_example_runs():
     """The standalone C-ABI example (no PyTorch) runs a periodic shear wave in
     three-step launches and checks its decay against exp(-nu k^2 t)."""
