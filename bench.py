@@ -5,8 +5,12 @@ Default workload: the 4096 x 4096 periodic transverse shear + acoustic wave
 deviation form, one lattice update per node per step.  A "step" is one pass of
 the hot path over the grid (gather along the 13 velocities, collide, store);
 FP64 diagnostics (conservation sums, Nusselt, symmetry) run once per
---diag-every steps inside the timed region.  The plain FP64 GPU step is timed
-on the same workload for the precision comparison.
+--diag-every steps inside the timed region.  The FP64 form (in its own
+autotuned launch) and the plain FP64 step (one step per launch) are timed on
+the same workload for the precision comparison.  Other workloads
+(--workload): cavities64 and channels128 (batched FP32 forms against the same
+domains as sequential plain FP64 contexts), wave32 and cavity256 (the small,
+cache-resident configurations, whole runs checked against the oracle).
 
 Prints ONE JSON line (rank 0).  `value` is MLUPS (million lattice updates per
 second) over the timed region with the state resident in HBM.
