@@ -7,7 +7,8 @@
  * to the 13 orthogonal moments of eq (d2q13-polynomes); rho, E, jx, jy are
  * conserved; the nine other moments relax toward the equilibria of eq
  * (d2q13-moments-equil) with the rates of eqs (d2q13-henon), (d2q13-diffusion),
- * (d2q13-sigma-qx); the body force (secs. 5, 8) is added to j; the inverse
+ * (d2q13-sigma-qx); the body force (secs. 5, 8) is added to j and the uniform
+ * energy source (sec. 9) to E; the inverse
  * transform gives the post-collision populations, which move along the 13
  * velocities (eq d2q13-vitesses, reach 1 and 2).  Links that leave the domain
  * through a wall come back by bounce-back (links with a tangential component,
