@@ -38,6 +38,18 @@ GRAPH_K = 120                 # steps per captured HIP graph (a multiple of 2 an
 ACCURACY_STEPS = 10000        # FP32 against FP64 on the GPU after this many steps (the stated FP32 bound's horizon)
 BYTES_PER_LU = {0: 208, 1: 104}  # 13 loads + 13 stores of populations, FP64 / FP32
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E
+# Vector ALU of the MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz, one wave64
+# VALU instruction per SIMD every 4 cycles.  FMA = 2 flops: 78.6 TFLOP/s in FP64
+# (the published vector peak) and in unpacked FP32 (the published 157.3 counts
+# packed FP32 instructions, which the library's build excludes).
+CLOCK_GHZ = 2.4
+SIMDS = 256 * 4
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * CLOCK_GHZ / 1e3
+# Floating-point operations of one collision (each add, subtract, multiply and
+# the reciprocal of rho counted once): the pair sums and differences, the 13
+# moments, the equilibria, the relaxation and the inverse of the pair-symmetric
+# form; +16 with the body force and energy-source terms.
+FLOPS_PER_LU = 177
 METRIC = "MLUPS and % of HBM roofline, FP32/batched vs plain FP64 GPU at stated error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_4096_traffic.json")
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step3_batched_traffic.json")
@@ -69,11 +81,11 @@ def launch_kernels(launch):
     return (3, tuple(launch["fused_tile"]), bool(launch["interior_kernel"]))
 
 
-def measured_traffic(key, launch, path=None):
-    """HBM bytes per launch of the timed form from the committed rocprofv3
-    counter runs, if they were taken on the current kernel source with the
-    same kernels (the configuration the default run chose, or one of the
-    alternates measured beside it); else None."""
+def measured_record(key, launch, path=None):
+    """The committed rocprofv3 counter record of the timed form (HBM bytes per
+    launch, VALU instructions per launch), if it was taken on the current
+    kernel source with the same kernels (the configuration the default run
+    chose, or one of the alternates measured beside it); else None."""
     try:
         with open(path or TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -83,8 +95,31 @@ def measured_traffic(key, launch, path=None):
         return None
     for rec in [t.get(key)] + t.get("alternates", {}).get(key, []):
         if rec and launch_kernels(rec["launch"]) == launch_kernels(launch):
-            return rec.get("bytes_per_launch")
+            return dict(rec, file=os.path.relpath(path or TRAFFIC_FILE, ROOT))
     return None
+
+
+def measured_traffic(key, launch, path=None):
+    """HBM bytes per launch of the timed form (see measured_record), or None."""
+    rec = measured_record(key, launch, path)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def measured_counters(key, launch, path=None):
+    rec = measured_record(key, launch, path)
+    if not rec or not rec.get("SQ_INSTS_VALU"):
+        return None
+    return {"SQ_INSTS_VALU": rec["SQ_INSTS_VALU"], "file": rec["file"]}
+
+
+def next_chunk(done, steps, diag_every):
+    """Steps of the next timed chunk and whether FP64 diagnostics follow it:
+    chunks end where the count of timed steps reaches a multiple of diag_every
+    (diagnostics then run, at exactly their stated rate) or at the end."""
+    if diag_every <= 0:
+        return steps - done, False
+    k = min(diag_every - done % diag_every, steps - done)
+    return k, (done + k) % diag_every == 0
 
 
 def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0):
@@ -113,19 +148,18 @@ def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0
     lat.step(warmup)
     d0 = lat.diagnostics()
     torch.cuda.synchronize()
-    chunk = diag_every if diag_every > 0 else steps
     ev = []
     t0 = time.perf_counter()
     done = 0
     while done < steps:
-        k = min(chunk, steps - done)
+        k, diag_now = next_chunk(done, steps, diag_every)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
         lat.step(k)
         b.record(stream)
         ev.append((a, b, k))
-        if diag_every > 0:
+        if diag_now:
             lat.diagnostics()  # FP64 reductions (synchronises)
         done += k
     torch.cuda.synchronize()
@@ -224,15 +258,14 @@ def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=Tru
     ev = []
     t0 = time.perf_counter()
     done = 0
-    chunk = diag_every if diag_every > 0 else steps
     while done < steps:
-        k = min(chunk, steps - done)
+        k, diag_now = next_chunk(done, steps, diag_every)
         a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         b.step(k)
         e.record(stream)
         ev.append((a, e, k))
-        if diag_every > 0:
+        if diag_now:
             b.diagnostics()
         done += k
     torch.cuda.synchronize()
@@ -392,22 +425,42 @@ def moment_errors(got, ref):
     return {"rho_rel": rho, "u_abs": u, "T_rel": T}
 
 
-def roofline(nodes, kernel_ms, precision, traffic=None, spl=1, bound=None):
-    """Algorithmic bytes per launch (26 population moves per lattice update,
-    spl updates per node per launch) over the launch's duration."""
-    achieved = BYTES_PER_LU[precision] * nodes * spl / (kernel_ms * 1e-3) / 1e9
-    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic}
+def roofline(nodes, kernel_ms, precision, traffic=None, spl=1, counters=None, sourced=False):
+    """Roofline of one launch that advances every node by spl steps.
+
+    HBM: the least a launch must move is one read and one write of the state,
+    26 populations per node (104 B FP32, 208 B FP64) whatever spl; `achieved`
+    is those bytes over the launch's average duration.  ALU: the collisions'
+    floating-point operations (FLOPS_PER_LU per update, spl updates per node)
+    over the same time, against the unpacked vector peak.  `bound` is the
+    ceiling whose lower bound on the launch time is larger (HBM for every form
+    here: about 6 flop/B against a machine balance near 10).  `traffic` is the
+    HBM bytes a launch moved (rocprofv3 FETCH_SIZE + WRITE_SIZE); `valu_issue`
+    the measured VALU instruction issue over the issue peak of the 1024 SIMDs
+    at 2.4 GHz (rocprofv3 SQ_INSTS_VALU), the resource that limits the
+    multi-step kernels in practice."""
+    t = kernel_ms * 1e-3
+    hbm_bytes = BYTES_PER_LU[precision] * nodes
+    flops = (FLOPS_PER_LU + (16 if sourced else 0)) * nodes * spl
+    hbm = hbm_bytes / t / 1e9
+    alu = flops / t / 1e12
+    t_hbm, t_alu = hbm_bytes / (HBM_PEAK_GBPS * 1e9), flops / (ALU_PEAK_TFLOPS * 1e12)
+    out = {"bound": "hbm" if t_hbm >= t_alu else "alu", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS,
+           "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBPS, 4), "traffic": traffic,
+           "steps_per_launch": spl, "bytes_per_launch": hbm_bytes,
+           "alu": {"achieved": round(alu, 2), "peak": round(ALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                   "frac": round(alu / ALU_PEAK_TFLOPS, 4), "flops_per_update": flops // (nodes * spl)}}
+    if out["bound"] == "alu":
+        out.update(achieved=out["alu"]["achieved"], peak=out["alu"]["peak"], unit="TFLOP/s",
+                   frac=out["alu"]["frac"])
     if traffic:
-        out["traffic_GBps"] = round(traffic / (kernel_ms * 1e-3) / 1e9, 1)
-    if spl > 1:
-        out["note"] = ("%d steps per launch: the algorithmic bytes are those of %d single steps, the HBM bytes "
-                       "moved are `traffic` (rocprofv3 counters)" % (spl, spl))
-        if bound:
-            out["note"] += "; " + bound
-        elif spl == 3:
-            out["note"] += ("; on the wave the three-step kernel is bound by vector ALU issue (FP32) or latency "
-                            "(FP64), profiles/step3_kernel_4096_counters.md")
+        out["traffic_GBps"] = round(traffic / t / 1e9, 1)
+        out["traffic_over_bytes"] = round(traffic / hbm_bytes, 3)
+    if counters and counters.get("SQ_INSTS_VALU"):
+        cap = SIMDS * CLOCK_GHZ * 1e9 * t / 4.0
+        out["valu_issue"] = {"frac": round(counters["SQ_INSTS_VALU"] / cap, 4), "clock_GHz": CLOCK_GHZ,
+                             "lane_ops_per_update": round(counters["SQ_INSTS_VALU"] * 64 / (nodes * spl), 1),
+                             "source": "rocprofv3 SQ_INSTS_VALU per launch, " + counters.get("file", "")}
     return out
 
 
@@ -511,10 +564,10 @@ def main_batched(args, copy_gbps):
                    "form": "fp32-deviation batched, one launch covers every domain", "launch": r32["cfg"],
                    "launch_choice": "fixed" if args.launch_fp32 else "autotuned on this device",
                    "graph_steps": graph_k, "diag_every": args.diag_every, "clamped_domains": clamped},
-        "roofline": roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, spl=r32["spl"],
+        "roofline": roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, spl=r32["spl"], sourced=True,
                              traffic=measured_traffic(args.workload, r32["cfg"], BATCH_TRAFFIC_FILE) if r32["cfg"] else None,
-                             bound="the general (wall) kernel is bound by vector ALU issue, "
-                                   "profiles/step3_wall_kernel_channels_counters.md"),
+                             counters=measured_counters(args.workload, r32["cfg"], BATCH_TRAFFIC_FILE)
+                             if r32["cfg"] else None),
         "cpu_baseline": cpu,
         "fp64_sequential": {"value": round(r64["mlups"], 1), "unit": "MLUPS",
                             "ms_per_step": round(r64["ms_per_step"], 5), "steps": fp64_steps,
@@ -764,11 +817,11 @@ def main():
         del m64
 
     roof32 = roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, measured_traffic("fp32", r32["launch"]),
-                      spl=r32["spl"])
+                      spl=r32["spl"], counters=measured_counters("fp32", r32["launch"]))
     roof64 = roofline(r64["nodes"], r64["kernel_ms_per_launch"], 0, measured_traffic("fp64", r64["launch"]),
-                      spl=r64["spl"])
+                      spl=r64["spl"], counters=measured_counters("fp64", r64["launch"]))
     roof64p = roofline(r64p["nodes"], r64p["kernel_ms_per_launch"], 0, measured_traffic("fp64_plain", r64p["launch"]),
-                       spl=1)
+                       spl=1, counters=measured_counters("fp64_plain", r64p["launch"]))
     out = {
         "metric": METRIC,
         "value": round(r32["mlups"], 1),
@@ -799,7 +852,7 @@ def main():
                                  "fp64": round(r64["kernel_ms_per_launch"], 5),
                                  "fp64_plain": round(r64p["kernel_ms_per_launch"], 5)},
         "copy_GBps": round(copy_gbps, 1),
-        "frac_of_copy": round(roof32["achieved"] / copy_gbps, 4),
+        "frac_of_copy": round(roof32["achieved"] / copy_gbps, 4) if roof32["unit"] == "GB/s" else None,
         "mass_drift": {"fp32": r32["mass_drift"], "fp64": r64["mass_drift"], "fp64_plain": r64p["mass_drift"]},
         "error": err,
         "kernel_source_sha": kernel_sha(),

@@ -103,7 +103,10 @@ typedef struct lbm13_ctx lbm13_ctx;
 
 /* Host-only: derive the constrained coefficients (eqs d2q13-henon,
  * d2q13-diffusion, d2q13-sigma-qx).  Returns LBM13_EUNSTABLE_PARAMS when a rate
- * leaves (0, 2) or Pr <= 0; `out` is filled in either case.  No device access. */
+ * (given or the derived s_q) leaves (0, 2), Pr <= 0, or A = 13 c1 + 95 + 2 E0
+ * <= 0 (then cs2 = A/52 and nu = sigma_XX A/104 are not positive); `out` is
+ * filled in either case.  No device access.  lbm13_set_params applies the same
+ * checks. */
 int lbm13_derive(const lbm13_params *p, lbm13_derived *out);
 
 /* Bytes of device workspace a single domain nx x ny in `precision` needs
@@ -176,14 +179,21 @@ int lbm13_fourier(lbm13_ctx *ctx, int kx, int ky, double out[8]);
 int lbm13_get_state(lbm13_ctx *ctx, double *dst);
 int lbm13_set_state(lbm13_ctx *ctx, const double *src);
 
-/* Raw checkpoint of the kept state: 13*ny*nx values of the storage precision
- * (8 bytes for LBM13_FP64, 4 for LBM13_FP32_DEV), the stored deviations from
- * the rest populations, dense [13][ny][nx], in the device buffer dst of
- * lbm13_state_bytes() bytes.  lbm13_load() restores it bit-exactly, so a run
- * resumed from a checkpoint equals the uninterrupted run.  Async. */
+/* Raw checkpoint of the kept state in the device buffer dst of dst_bytes >=
+ * lbm13_state_bytes() bytes: a 256-byte header (magic "LBM13CK", format
+ * version, precision, nx, ny, steps taken, payload bytes) followed by 13*ny*nx
+ * values of the storage precision (8 bytes for LBM13_FP64, 4 for
+ * LBM13_FP32_DEV), the stored deviations from the rest populations, dense
+ * [13][ny][nx].  lbm13_save is async; EINVAL when dst is NULL or too small,
+ * ESTATE before any state exists.  lbm13_load(ctx, src, src_bytes) requires
+ * src_bytes == lbm13_state_bytes(), reads the header back (synchronises the
+ * stream) and returns EINVAL, changing nothing, unless it names this context's
+ * nx, ny and precision; it then restores the populations bit-exactly and the
+ * step counter, so a run resumed from a checkpoint equals the uninterrupted
+ * run.  src must be a device pointer. */
 size_t lbm13_state_bytes(const lbm13_ctx *ctx);
-int lbm13_save(lbm13_ctx *ctx, void *dst);
-int lbm13_load(lbm13_ctx *ctx, const void *src);
+int lbm13_save(lbm13_ctx *ctx, void *dst, size_t dst_bytes);
+int lbm13_load(lbm13_ctx *ctx, const void *src, size_t src_bytes);
 
 /* Number of steps taken since the last lbm13_init_moments() (which resets it). */
 long long lbm13_steps_done(const lbm13_ctx *ctx);
@@ -274,9 +284,11 @@ int lbm13_batch_moments(lbm13_batch *b, int i, double *rho, double *ux, double *
 int lbm13_batch_diagnostics(lbm13_batch *b, double *out);
 int lbm13_batch_get_state(lbm13_batch *b, int i, double *dst);
 int lbm13_batch_set_state(lbm13_batch *b, int i, const double *src);
+/* Checkpoints of domain i, as lbm13_save / lbm13_load; lbm13_batch_load keeps
+ * the batch's step counter (shared by every domain). */
 size_t lbm13_batch_state_bytes(const lbm13_batch *b, int i);
-int lbm13_batch_save(lbm13_batch *b, int i, void *dst);
-int lbm13_batch_load(lbm13_batch *b, int i, const void *src);
+int lbm13_batch_save(lbm13_batch *b, int i, void *dst, size_t dst_bytes);
+int lbm13_batch_load(lbm13_batch *b, int i, const void *src, size_t src_bytes);
 int lbm13_batch_set_tile(lbm13_batch *b, int tile_x, int tile_y);
 int lbm13_batch_autotune(lbm13_batch *b, int steps, int *tile_x, int *tile_y);
 int lbm13_batch_use_graph(lbm13_batch *b, int k);

@@ -143,7 +143,8 @@ void or13_velocities(int *vx, int *vy)
 /* of the scheme: cs2 from the first-order system (d2q13-equiv-edp-ordre-1), */
 /* kappa = nu / Pr by definition of the Prandtl number, nu from the second-  */
 /* order expansion, kappa_E = E-conductivity in steady conduction (j = 0).   */
-/* Returns 0, or -1 when a rate leaves (0, 2) or the inputs are degenerate.  */
+/* Returns 0, or -1 when a rate leaves (0, 2), A = 13 c1 + 95 + 2 E0 <= 0    */
+/* (no positive sound speed or viscosity) or the inputs are degenerate.     */
 int or13_derive(const or13_params *p, or13_derived *d)
 {
     double c1 = p->c1, E0 = p->E0, k2 = p->k2, ceE = p->c_epsE;
@@ -167,6 +168,8 @@ int or13_derive(const or13_params *p, or13_derived *d)
     for (int i = 0; i < 6; ++i)
         if (!(rates[i] > 0.0 && rates[i] < 2.0)) return -1;
     if (!(d->Y != 0.0) || !(p->Pr > 0.0)) return -1;
+    /* A <= 0: the squared sound speed A/52 and the viscosity sigma_XX A/104 are not positive */
+    if (!(d->A > 0.0) || !(d->nu > 0.0) || !(d->cs2 > 0.0)) return -1;
     return 0;
 }
 

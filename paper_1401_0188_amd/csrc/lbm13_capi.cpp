@@ -47,6 +47,7 @@ template <typename R>
 hipError_t launch_get_state(int, int, const R*, const Dom<R>*, int, double*, hipStream_t);
 template <typename R>
 hipError_t launch_set_state(int, int, R*, const Dom<R>*, int, const double*, hipStream_t);
+hipError_t launch_ckpt_header(const CkptHeader&, void*, hipStream_t);
 }  // namespace lbm13
 
 using lbm13::Dom;
@@ -182,6 +183,9 @@ int derive(const lbm13_params* p, lbm13_derived* d) {
         if (!(r > 0.0 && r < 2.0)) return LBM13_EUNSTABLE_PARAMS;
     if (!(p->Pr > 0.0) || !(Y != 0.0) || !std::isfinite(d->c_eps_rho) || !std::isfinite(d->h2))
         return LBM13_EUNSTABLE_PARAMS;
+    // A = 13 c1 + 95 + 2 E0 <= 0 makes cs2 = A/52 and nu = sigma_XX A/104 non-positive: no
+    // sound and no viscosity, whatever the rates.
+    if (!(A > 0.0) || !(d->nu > 0.0) || !(d->cs2 > 0.0)) return LBM13_EUNSTABLE_PARAMS;
     return LBM13_OK;
 }
 
@@ -944,9 +948,13 @@ int lbm13_batch_set_state(lbm13_batch* b, int i, const double* src) {
     return LBM13_OK;
 }
 
+static size_t payload_bytes(const lbm13_batch* b, int i) {
+    return (size_t)13 * b->nx[i] * b->ny[i] * (b->precision == LBM13_FP64 ? 8 : 4);
+}
+
 size_t lbm13_batch_state_bytes(const lbm13_batch* b, int i) {
     if (!b || i < 0 || i >= b->count) return 0;
-    return (size_t)13 * b->nx[i] * b->ny[i] * (b->precision == LBM13_FP64 ? 8 : 4);
+    return lbm13::kCkptHeaderBytes + payload_bytes(b, i);
 }
 
 // Raw copies between the padded planes and a dense [13][ny][nx] array.
@@ -968,21 +976,51 @@ static int raw_copy(lbm13_batch* b, int i, void* dense, const void* dense_src) {
     return LBM13_OK;
 }
 
-int lbm13_batch_save(lbm13_batch* b, int i, void* dst) {
+int lbm13_batch_save(lbm13_batch* b, int i, void* dst, size_t dst_bytes) {
     if (!check_index(b, i) || !dst) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    if (dst_bytes < lbm13_batch_state_bytes(b, i)) return fail(b, LBM13_EINVAL, "checkpoint buffer too small");
     if (!b->has_state[i]) return fail(b, LBM13_ESTATE, "no state");
-    return raw_copy(b, i, dst, nullptr);
+    lbm13::CkptHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "LBM13CK", 8);
+    h.version = lbm13::kCkptVersion;
+    h.precision = b->precision;
+    h.nx = b->nx[i];
+    h.ny = b->ny[i];
+    h.steps = b->steps;
+    h.payload = payload_bytes(b, i);
+    hipError_t e = lbm13::launch_ckpt_header(h, dst, b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "checkpoint header");
+    return raw_copy(b, i, static_cast<char*>(dst) + lbm13::kCkptHeaderBytes, nullptr);
 }
 
-int lbm13_batch_load(lbm13_batch* b, int i, const void* src) {
+// Reads the checkpoint's header back (synchronising the stream) and accepts it
+// only for this domain's size and precision; restores the populations and,
+// when restore_steps, the step counter.
+static int load_impl(lbm13_batch* b, int i, const void* src, size_t src_bytes, bool restore_steps) {
     if (!check_index(b, i) || !src) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    if (src_bytes != lbm13_batch_state_bytes(b, i))
+        return fail(b, LBM13_EINVAL, "checkpoint size does not match this domain");
     if (!b->has_params[i]) return fail(b, LBM13_ESTATE, "set_params first");
-    int st = raw_copy(b, i, nullptr, src);
+    lbm13::CkptHeader h;
+    hipError_t e = hipMemcpyAsync(&h, src, sizeof h, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(b, e, "checkpoint header read");
+    if (std::memcmp(h.magic, "LBM13CK", 8) != 0 || h.version != lbm13::kCkptVersion)
+        return fail(b, LBM13_EINVAL, "not a checkpoint of this library");
+    if (h.precision != b->precision || h.nx != b->nx[i] || h.ny != b->ny[i] || h.payload != payload_bytes(b, i))
+        return fail(b, LBM13_EINVAL, "checkpoint of another domain size or precision");
+    int st = raw_copy(b, i, nullptr, static_cast<const char*>(src) + lbm13::kCkptHeaderBytes);
     if (st != LBM13_OK) return st;
-    hipError_t e = fill_side_any(b, i);
+    e = fill_side_any(b, i);
     if (e != hipSuccess) return hip_fail(b, e, "side fill launch");
     b->has_state[i] = 1;
+    if (restore_steps) b->steps = h.steps;
     return LBM13_OK;
+}
+
+int lbm13_batch_load(lbm13_batch* b, int i, const void* src, size_t src_bytes) {
+    return load_impl(b, i, src, src_bytes, false);
 }
 
 int lbm13_batch_set_tile(lbm13_batch* b, int tile_x, int tile_y) {
@@ -1121,9 +1159,13 @@ long long lbm13_steps_done(const lbm13_ctx* c) { return c && c->b ? c->b->steps 
 
 size_t lbm13_state_bytes(const lbm13_ctx* c) { return c ? lbm13_batch_state_bytes(c->b, 0) : 0; }
 
-int lbm13_save(lbm13_ctx* c, void* dst) { return c ? lbm13_batch_save(c->b, 0, dst) : LBM13_EINVAL; }
+int lbm13_save(lbm13_ctx* c, void* dst, size_t dst_bytes) {
+    return c ? lbm13_batch_save(c->b, 0, dst, dst_bytes) : LBM13_EINVAL;
+}
 
-int lbm13_load(lbm13_ctx* c, const void* src) { return c ? lbm13_batch_load(c->b, 0, src) : LBM13_EINVAL; }
+int lbm13_load(lbm13_ctx* c, const void* src, size_t src_bytes) {
+    return c ? load_impl(c->b, 0, src, src_bytes, true) : LBM13_EINVAL;
+}
 
 int lbm13_set_tile(lbm13_ctx* c, int tile_x, int tile_y) {
     return c ? lbm13_batch_set_tile(c->b, tile_x, tile_y) : LBM13_EINVAL;

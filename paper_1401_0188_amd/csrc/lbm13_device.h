@@ -91,6 +91,19 @@ struct FusedFits {
     static constexpr bool value = 13 * (TW + 4) * (TH + 4) * sizeof(R) + 6 * (TW + TH + 8) * sizeof(R) <= 163840;
 };
 
+// Header of a raw checkpoint: the first kCkptHeaderBytes bytes of the blob,
+// followed by the stored deviations of one domain, dense [13][ny][nx].
+struct CkptHeader {
+    char magic[8];              // "LBM13CK" and a terminating zero
+    int version;                // kCkptVersion
+    int precision;              // LBM13_FP64 or LBM13_FP32_DEV
+    int nx, ny;
+    long long steps;            // steps taken when the checkpoint was written
+    unsigned long long payload;  // bytes of populations after the header
+};
+constexpr int kCkptVersion = 1;
+constexpr size_t kCkptHeaderBytes = 256;
+
 constexpr int kDiagPartials = 10;  // per-tile partial reductions
 constexpr int kDiagOut = 16;       // values per domain
 

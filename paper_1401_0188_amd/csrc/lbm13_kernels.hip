@@ -1631,6 +1631,16 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
     return hipGetLastError();
 }
 
+// Writes a checkpoint header (passed by value, so the launch owns its copy).
+__global__ __launch_bounds__(64) void ckpt_header_kernel(CkptHeader h, CkptHeader* __restrict__ dst) {
+    if (threadIdx.x == 0) *dst = h;
+}
+
+hipError_t launch_ckpt_header(const CkptHeader& h, void* dst, hipStream_t s) {
+    ckpt_header_kernel<<<1, 64, 0, s>>>(h, static_cast<CkptHeader*>(dst));
+    return hipGetLastError();
+}
+
 #define LBM13_INSTANTIATE(R)                                                                                      \
     template hipError_t launch_step<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, const Tile*, int, \
                                        R*, int, hipStream_t);                                                     \

@@ -94,8 +94,8 @@ def lib():
         "lbm13_set_state": (i32, [vp, dp]),
         "lbm13_steps_done": (i64, [vp]),
         "lbm13_state_bytes": (sz, [vp]),
-        "lbm13_save": (i32, [vp, vp]),
-        "lbm13_load": (i32, [vp, vp]),
+        "lbm13_save": (i32, [vp, vp, sz]),
+        "lbm13_load": (i32, [vp, vp, sz]),
         "lbm13_set_tile": (i32, [vp, i32, i32]),
         "lbm13_autotune": (i32, [vp, i32, ip, ip]),
         "lbm13_use_graph": (i32, [vp, i32]),
@@ -116,8 +116,8 @@ def lib():
         "lbm13_batch_get_state": (i32, [vp, i32, dp]),
         "lbm13_batch_set_state": (i32, [vp, i32, dp]),
         "lbm13_batch_state_bytes": (sz, [vp, i32]),
-        "lbm13_batch_save": (i32, [vp, i32, vp]),
-        "lbm13_batch_load": (i32, [vp, i32, vp]),
+        "lbm13_batch_save": (i32, [vp, i32, vp, sz]),
+        "lbm13_batch_load": (i32, [vp, i32, vp, sz]),
         "lbm13_batch_set_tile": (i32, [vp, i32, i32]),
         "lbm13_batch_autotune": (i32, [vp, i32, ip, ip]),
         "lbm13_batch_use_graph": (i32, [vp, i32]),
@@ -175,6 +175,20 @@ def _torch():
     if not torch.cuda.is_available():
         raise RuntimeError("lbm13 needs a GPU: torch.cuda.is_available() is False")
     return torch
+
+
+def _checkpoint_blob(blob, torch, nbytes):
+    """A checkpoint handed to load(): a contiguous device tensor of exactly the
+    context's checkpoint size.  Checked on the host, so no copy is issued from
+    a wrong buffer."""
+    if not isinstance(blob, torch.Tensor) or not blob.is_cuda:
+        raise LBM13Error(EINVAL, "checkpoint must be a device tensor")
+    if not blob.is_contiguous():
+        raise LBM13Error(EINVAL, "checkpoint tensor must be contiguous")
+    if blob.numel() * blob.element_size() != nbytes:
+        raise LBM13Error(EINVAL, "checkpoint has %d bytes, this domain's has %d"
+                         % (blob.numel() * blob.element_size(), nbytes))
+    return blob
 
 
 def _dev_f64(a, torch, n):
@@ -307,17 +321,24 @@ class Lattice(_Base):
         self._check(lib().lbm13_set_state(self._h, ctypes.c_void_p(t.data_ptr())))
 
     def save(self):
-        """Raw checkpoint (device uint8 tensor) of the stored working-precision state."""
+        """Raw checkpoint (device uint8 tensor): header (size, precision, steps)
+        and the stored working-precision state."""
         torch = _torch()
-        out = torch.empty(int(lib().lbm13_state_bytes(self._h)), dtype=torch.uint8, device="cuda")
+        nbytes = int(lib().lbm13_state_bytes(self._h))
+        out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self._use([out])
-        self._check(lib().lbm13_save(self._h, ctypes.c_void_p(out.data_ptr())))
+        self._check(lib().lbm13_save(self._h, ctypes.c_void_p(out.data_ptr()), nbytes))
         return self._hand_over([out])[0]
 
     def load(self, blob):
+        """Restore a checkpoint of this context's size and precision (and its
+        step counter); anything else raises LBM13Error(EINVAL)."""
+        torch = _torch()
+        nbytes = int(lib().lbm13_state_bytes(self._h))
+        blob = _checkpoint_blob(blob, torch, nbytes)
         self._keep = [blob]
         self._use([blob])
-        self._check(lib().lbm13_load(self._h, ctypes.c_void_p(blob.data_ptr())))
+        self._check(lib().lbm13_load(self._h, ctypes.c_void_p(blob.data_ptr()), nbytes))
 
     def steps_done(self) -> int:
         return int(lib().lbm13_steps_done(self._h))
@@ -436,15 +457,19 @@ class Batch(_Base):
 
     def save(self, i: int):
         torch = _torch()
-        out = torch.empty(int(lib().lbm13_batch_state_bytes(self._h, int(i))), dtype=torch.uint8, device="cuda")
+        nbytes = int(lib().lbm13_batch_state_bytes(self._h, int(i)))
+        out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self._use([out])
-        self._check(lib().lbm13_batch_save(self._h, int(i), ctypes.c_void_p(out.data_ptr())))
+        self._check(lib().lbm13_batch_save(self._h, int(i), ctypes.c_void_p(out.data_ptr()), nbytes))
         return self._hand_over([out])[0]
 
     def load(self, i: int, blob):
+        torch = _torch()
+        nbytes = int(lib().lbm13_batch_state_bytes(self._h, int(i)))
+        blob = _checkpoint_blob(blob, torch, nbytes)
         self._keep[("blob", i)] = blob
         self._use([blob])
-        self._check(lib().lbm13_batch_load(self._h, int(i), ctypes.c_void_p(blob.data_ptr())))
+        self._check(lib().lbm13_batch_load(self._h, int(i), ctypes.c_void_p(blob.data_ptr()), nbytes))
 
     def set_tile(self, tile_x: int, tile_y: int):
         self._check(lib().lbm13_batch_set_tile(self._h, int(tile_x), int(tile_y)))

@@ -63,6 +63,22 @@ def test_derive_rejects_out_of_range_rates():
     assert lbm13.derive()[0] == lbm13.OK
 
 
+@pytest.mark.parametrize("kw", [dict(c1=-8.0, E0=0.0, c_epsE=-30.0),     # A = -9, every rate in (0, 2)
+                                dict(c1=-7.0, E0=-2.0, c_epsE=-2.5),     # A = 0
+                                dict(c1=-3.0, E0=-28.5, c_epsE=-2.5)])   # A = -1 through E0
+def test_derive_rejects_nonpositive_sound_speed(kw):
+    """A = 13 c1 + 95 + 2 E0 <= 0 leaves no positive sound speed (cs2 = A/52)
+    nor viscosity (nu = sigma_XX A/104): both codes return the unstable code,
+    even where the given and derived rates all lie in (0, 2)."""
+    st_l, dl = lbm13.derive(**kw)
+    st_o, do = oracle.derive(oracle.params(**kw))
+    assert dl["A"] <= 0.0 and do["A"] <= 0.0
+    assert st_l == lbm13.EUNSTABLE_PARAMS
+    assert st_o != 0
+    if kw["c_epsE"] == -30.0:
+        assert 0.0 < dl["s_q"] < 2.0  # only the sign of A rules this set out
+
+
 def test_workspace_sizes():
     L = lbm13.lib()
     a = L.lbm13_workspace_bytes(4096, 4096, lbm13.FP32_DEV)
@@ -119,3 +135,12 @@ def test_no_device_fails_loudly():
         lbm13.Lattice(8, 8, lbm13.FP64)
     with pytest.raises(Exception):
         lbm13.Batch([(8, 8), (5, 3)], lbm13.FP32_DEV)
+
+
+def test_checkpoint_blob_checked_on_host():
+    """load() validates the checkpoint tensor before any copy is issued."""
+    import torch
+    with pytest.raises(lbm13.LBM13Error, match="device tensor"):
+        lbm13._checkpoint_blob(torch.zeros(64, dtype=torch.uint8), torch, 64)
+    with pytest.raises(lbm13.LBM13Error, match="device tensor"):
+        lbm13._checkpoint_blob(b"\0" * 64, torch, 64)

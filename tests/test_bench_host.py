@@ -64,3 +64,38 @@ def test_more_than_one_gpu_is_refused():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("steps,diag_every", [(20, 1000), (2040, 1000), (3000, 1000), (7, 3), (5, 0)])
+def test_diagnostics_run_at_their_stated_rate(steps, diag_every):
+    """Timed chunks cover the steps exactly; diagnostics follow only the chunks
+    that end on a multiple of diag_every (none in a run shorter than that)."""
+    done, diags = 0, 0
+    while done < steps:
+        k, d = bench.next_chunk(done, steps, diag_every)
+        assert k > 0
+        done += k
+        diags += d
+        if d:
+            assert done % diag_every == 0
+    assert done == steps
+    assert diags == (steps // diag_every if diag_every > 0 else 0)
+
+
+@pytest.mark.parametrize("precision,spl", [(1, 1), (1, 3), (0, 2), (0, 3)])
+def test_roofline_fraction_is_a_fraction(precision, spl):
+    """The HBM roofline of a k-step launch counts one read and one write of the
+    state per launch: a launch as fast as the peak allows gives frac 1, and
+    k does not enter the bytes."""
+    nodes = 4096 * 4096
+    ideal_ms = bench.BYTES_PER_LU[precision] * nodes / (bench.HBM_PEAK_GBPS * 1e9) * 1e3
+    r = bench.roofline(nodes, ideal_ms, precision, spl=spl)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert r["frac"] == pytest.approx(1.0, rel=1e-3)
+    assert r["alu"]["frac"] < 1.0
+    slower = bench.roofline(nodes, 2 * ideal_ms, precision, spl=spl,
+                            counters={"SQ_INSTS_VALU": 1.0e8, "file": "x"})
+    assert slower["frac"] == pytest.approx(0.5, rel=1e-3)
+    cap = bench.SIMDS * bench.CLOCK_GHZ * 1e9 * 2 * ideal_ms * 1e-3 / 4
+    assert slower["valu_issue"]["frac"] == pytest.approx(1.0e8 / cap, rel=1e-3)
+    assert bench.ALU_PEAK_TFLOPS == pytest.approx(78.6, abs=0.1)

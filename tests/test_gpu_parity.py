@@ -753,6 +753,7 @@ def test_checkpoint_resume_is_bit_exact(precision, spl):
     lat.step(30)
     s1 = lat.get_state().cpu().numpy()
     lat.load(blob)
+    assert lat.steps_done() == 30  # the header restores the step counter
     lat.step(30)
     assert np.array_equal(lat.get_state().cpu().numpy(), s1)
     # the absolute FP64 view round-trips within the rounding of one subtraction
@@ -760,6 +761,40 @@ def test_checkpoint_resume_is_bit_exact(precision, spl):
     back = lat.get_state()
     tol = 1e-16 if precision == 0 else 1e-8
     assert float((back - absolute).abs().max()) <= tol
+
+
+def test_checkpoint_load_rejects_foreign_blobs():
+    """load() takes only a checkpoint of the same domain size and precision:
+    host tensors, strided views, blobs of another size and a blob of the same
+    byte count from another shape and precision are refused before any
+    population is copied, and the context keeps its state."""
+    import torch
+    lbm13 = _lb()
+    say("checkpoint rejections")
+    # FP64 32x32 and FP32 64x32 hold the same number of payload bytes
+    a = lbm13.Lattice(32, 32, lbm13.FP64)
+    b = lbm13.Lattice(64, 32, lbm13.FP32_DEV)
+    for lat, n in ((a, 32), (b, 64)):
+        lat.set_params()
+        lat.init_moments(*workloads.shear_acoustic(n, 32))
+        lat.step(3)
+    blob_a, blob_b = a.save(), b.save()
+    assert blob_a.numel() == blob_b.numel()
+    before = a.get_state().cpu().numpy()
+    for bad in (blob_a.cpu(), blob_a[::2], blob_a[:-8], torch.zeros(blob_a.numel() + 8, dtype=torch.uint8,
+                                                                   device="cuda")):
+        with pytest.raises(lbm13.LBM13Error) as e:
+            a.load(bad)
+        assert e.value.code == lbm13.EINVAL
+    for bad in (blob_b, torch.zeros_like(blob_a)):  # right size, wrong header
+        with pytest.raises(lbm13.LBM13Error) as e:
+            a.load(bad)
+        assert e.value.code == lbm13.EINVAL
+    assert np.array_equal(a.get_state().cpu().numpy(), before)
+    a.load(blob_a)
+    assert np.array_equal(a.get_state().cpu().numpy(), before)
+    a.destroy()
+    b.destroy()
 
 
 def test_error_paths():
