@@ -49,22 +49,26 @@ def _meq(m, p, d):
     return out
 
 
-def amplification(p, k, U=(0.0, 0.0), rho=1.0, E=None):
-    """Amplification matrix for wave vector k about (rho, j = rho U, E)."""
-    st, d = oracle.derive(p)
+def amplification(p, k, U=(0.0, 0.0), rho=1.0, E=None, derived=None):
+    """Amplification matrix for wave vector k about (rho, j = rho U, E).
+
+    `derived` replaces the oracle's derived coefficients (h1, k1, h2, c2, ...)
+    when given.  The Jacobian is taken by a complex step (the equilibria are
+    rational in the conserved moments), exact to rounding."""
+    d = oracle.derive(p)[1] if derived is None else derived
     M = moment_matrix()
     D = (M * M).sum(1)
     Minv = M.T / D
     if E is None:
         E = p.E0
-    m0 = np.zeros(13)
+    m0 = np.zeros(13, dtype=complex)
     m0[0], m0[1], m0[4], m0[5] = rho, E, rho * U[0], rho * U[1]
     J = np.zeros((13, 13))
-    h = 1e-6
+    h = 1e-30
     for c in (0, 1, 4, 5):
-        e = np.zeros(13)
-        e[c] = h
-        J[:, c] = (_meq(m0 + e, p, d) - _meq(m0 - e, p, d)) / (2 * h)
+        e = np.zeros(13, dtype=complex)
+        e[c] = 1j * h
+        J[:, c] = _meq(m0 + e, p, d).imag / h
     s = np.array([0, 0, p.s_eps, p.s_varpi, 0, 0, d["s_q"], d["s_q"], p.s_rx, p.s_rx,
                   p.s_XX, p.s_XX, p.s_XXe])
     C = Minv @ (np.eye(13) - np.diag(s) @ (np.eye(13) - J)) @ M
