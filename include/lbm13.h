@@ -260,8 +260,9 @@ int lbm13_set_interior_kernel(lbm13_ctx *ctx, int on);
  * events; never the workspace, which the caller may free once this returns. */
 int lbm13_destroy(lbm13_ctx *ctx);
 
-/* Message of the last failing call on ctx ("" if none; a static message when
- * ctx is NULL). */
+/* Message of the last failing call on ctx ("" if none).  With ctx NULL: the
+ * message of the last failed lbm13_create / lbm13_batch_create on the calling
+ * thread that got past argument checks, else a static message. */
 const char *lbm13_last_error(const lbm13_ctx *ctx);
 
 /* ------------------------------------------------------------------------ */

@@ -228,6 +228,7 @@ struct lbm13_batch {
     int split = 1;                        // 1: interior tiles run the compact-LDS kernel
     int tile_x = 64, tile_y = 8;
     int cur = 0;                          // buffer holding the current state
+    char* bufp[2] = {nullptr, nullptr};   // the two population buffers
     long long steps = 0;
     int graph_k = 0;
     int graph_flip = 0;                   // 1 when a captured graph has an odd number of launches
@@ -239,6 +240,9 @@ struct lbm13_batch {
 struct lbm13_ctx {
     lbm13_batch* b = nullptr;
 };
+
+// Message of the last failed create on this thread (no context exists to hold it).
+static thread_local std::string g_create_err;
 
 namespace {
 
@@ -262,7 +266,15 @@ Dom<R>* dom_host(lbm13_batch* b, int d) {
 
 template <typename R>
 R* buf(lbm13_batch* b, int which) {
-    return reinterpret_cast<R*>(b->ws + (which ? b->L.bufB : b->L.bufA));
+    return reinterpret_cast<R*>(b->bufp[which]);
+}
+
+// Host data to the workspace at byte offset `off` (an async copy: the host
+// data must live until it runs; the callers keep it in the batch and
+// synchronise).
+hipError_t upload(lbm13_batch* b, size_t off, const void* host, size_t bytes) {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(b->ws + off, host, bytes, hipMemcpyHostToDevice, b->stream);
 }
 
 template <typename R>
@@ -407,28 +419,19 @@ int rebuild(lbm13_batch* b) {
     if (b->precision == LBM13_FP64) set_tile_ranges<double>(b);
     else set_tile_ranges<float>(b);
     hipError_t e;
-    e = hipMemcpyAsync(b->ws + b->L.tiles_all, b->all.data(), sizeof(Tile) * b->all.size(), hipMemcpyHostToDevice,
-                       b->stream);
+    e = upload(b, b->L.tiles_all, b->all.data(), sizeof(Tile) * b->all.size());
     if (e != hipSuccess) return hip_fail(b, e, "upload tile table");
-    e = hipMemcpyAsync(b->ws + b->L.tiles_run, b->run.data(), sizeof(Tile) * b->run.size(), hipMemcpyHostToDevice,
-                       b->stream);
+    e = upload(b, b->L.tiles_run, b->run.data(), sizeof(Tile) * b->run.size());
     if (e != hipSuccess) return hip_fail(b, e, "upload tile table");
-    e = hipMemcpyAsync(b->ws + b->L.tiles_fused, b->fused.data(), sizeof(Tile) * b->fused.size(),
-                       hipMemcpyHostToDevice, b->stream);
+    e = upload(b, b->L.tiles_fused, b->fused.data(), sizeof(Tile) * b->fused.size());
     if (e != hipSuccess) return hip_fail(b, e, "upload fused tile table");
-    if (!b->fused3.empty()) {
-        e = hipMemcpyAsync(b->ws + b->L.tiles_fused3, b->fused3.data(), sizeof(Tile) * b->fused3.size(),
-                           hipMemcpyHostToDevice, b->stream);
-        if (e != hipSuccess) return hip_fail(b, e, "upload three-step tile table");
-    }
-    if (!b->lines.empty()) {
-        e = hipMemcpyAsync(b->ws + b->L.lines, b->lines.data(), sizeof(WallLine) * b->lines.size(),
-                           hipMemcpyHostToDevice, b->stream);
-        if (e != hipSuccess) return hip_fail(b, e, "upload wall lines");
-    }
-    e = hipMemcpyAsync(b->ws + b->L.doms, b->dom_host.data(), b->dom_host.size(), hipMemcpyHostToDevice, b->stream);
+    e = upload(b, b->L.tiles_fused3, b->fused3.data(), sizeof(Tile) * b->fused3.size());
+    if (e != hipSuccess) return hip_fail(b, e, "upload three-step tile table");
+    e = upload(b, b->L.lines, b->lines.data(), sizeof(WallLine) * b->lines.size());
+    if (e != hipSuccess) return hip_fail(b, e, "upload wall lines");
+    e = upload(b, b->L.doms, b->dom_host.data(), b->dom_host.size());
     if (e != hipSuccess) return hip_fail(b, e, "upload domain table");
-    e = hipStreamSynchronize(b->stream);
+    e = hipStreamSynchronize(b->stream);  // the async copies read the host tables
     if (e != hipSuccess) return hip_fail(b, e, "synchronise");
     drop_graphs(b);
     return LBM13_OK;
@@ -655,7 +658,7 @@ int step_impl(lbm13_batch* b, long long n) {
         n -= b->graph_k;
         b->steps += b->graph_k;
     }
-    if (b->spl >= 2 && n >= 2) {
+    if (b->spl >= 2 && n >= 2 && b->split) {  // with the interior kernel off every launch is one kernel
         hipError_t e = ensure_aux(b);
         if (e != hipSuccess) return hip_fail(b, e, "create auxiliary stream");
     }
@@ -779,6 +782,8 @@ int lbm13_batch_create(int count, const int* nx, const int* ny, int precision, v
     b->ny.assign(ny, ny + count);
     b->L = L;
     b->ws = static_cast<char*>(workspace);
+    b->bufp[0] = b->ws + L.bufA;
+    b->bufp[1] = b->ws + L.bufB;
     b->stream = static_cast<hipStream_t>(stream);
     b->dom_host.assign(dom_size(b) * count, 0);
     b->coef_host.assign((size_t)kCoef * count, 0.0);
@@ -789,6 +794,7 @@ int lbm13_batch_create(int count, const int* nx, const int* ny, int precision, v
     b->fth = precision == LBM13_FP64 ? lbm13::Fused<double>::TH : lbm13::Fused<float>::TH;
     int st = rebuild(b);
     if (st) {
+        g_create_err = b->err;
         delete b;
         return st;
     }
@@ -812,8 +818,8 @@ int lbm13_batch_set_params(lbm13_batch* b, int i, const lbm13_params* p, const l
     for (int w = 0; w < 4; ++w) b->sides_kind[4 * i + w] = sides[w].kind;
     if (b->precision == LBM13_FP64) fill_dom<double>(b, i, p, sides, &dv);
     else fill_dom<float>(b, i, p, sides, &dv);
-    hipError_t e = hipMemcpyAsync(b->ws + b->L.coef + sizeof(double) * kCoef * i, &b->coef_host[(size_t)kCoef * i],
-                                  sizeof(double) * kCoef, hipMemcpyHostToDevice, b->stream);
+    hipError_t e = upload(b, b->L.coef + sizeof(double) * kCoef * i, &b->coef_host[(size_t)kCoef * i],
+                          sizeof(double) * kCoef);
     if (e != hipSuccess) return hip_fail(b, e, "upload coefficients");
     b->has_params[i] = 1;
     st = rebuild(b);
@@ -960,7 +966,7 @@ size_t lbm13_batch_state_bytes(const lbm13_batch* b, int i) {
 // Raw copies between the padded planes and a dense [13][ny][nx] array.
 static int raw_copy(lbm13_batch* b, int i, void* dense, const void* dense_src) {
     const size_t es = b->precision == LBM13_FP64 ? 8 : 4;
-    char* plane0 = b->ws + (b->cur ? b->L.bufB : b->L.bufA) + es * (size_t)b->L.off[i];
+    char* plane0 = b->bufp[b->cur] + es * (size_t)b->L.off[i];
     const size_t row = es * b->nx[i], pitch = es * b->L.pitch[i], plane = es * (size_t)b->L.plane[i];
     const size_t dplane = row * b->ny[i];
     for (int q = 0; q < 13; ++q) {
@@ -1106,7 +1112,10 @@ int lbm13_batch_destroy(lbm13_batch* b) {
     return LBM13_OK;
 }
 
-const char* lbm13_batch_last_error(const lbm13_batch* b) { return b ? b->err.c_str() : "null batch"; }
+const char* lbm13_batch_last_error(const lbm13_batch* b) {
+    if (b) return b->err.c_str();
+    return g_create_err.empty() ? "null batch" : g_create_err.c_str();
+}
 
 // =========================================================================== single-domain API
 
@@ -1198,6 +1207,9 @@ int lbm13_destroy(lbm13_ctx* c) {
     return st;
 }
 
-const char* lbm13_last_error(const lbm13_ctx* c) { return c ? lbm13_batch_last_error(c->b) : "null context"; }
+const char* lbm13_last_error(const lbm13_ctx* c) {
+    if (c) return lbm13_batch_last_error(c->b);
+    return g_create_err.empty() ? "null context" : g_create_err.c_str();
+}
 
 }  // extern "C"

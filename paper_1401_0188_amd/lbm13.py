@@ -263,7 +263,7 @@ class Lattice(_Base):
         st = L.lbm13_create(self.nx, self.ny, self.precision, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != OK:
-            raise LBM13Error(st, "lbm13_create failed")
+            raise LBM13Error(st, "lbm13_create failed: " + (L.lbm13_last_error(None) or b"").decode())
         self._h = h
         self.derived = None
         self._keep = []
@@ -395,7 +395,7 @@ class Batch(_Base):
         st = L.lbm13_batch_create(self.count, nx, ny, self.precision, ctypes.c_void_p(self.workspace.data_ptr()),
                                   nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != OK:
-            raise LBM13Error(st, "lbm13_batch_create failed")
+            raise LBM13Error(st, "lbm13_batch_create failed: " + (L.lbm13_batch_last_error(None) or b"").decode())
         self._h = h
         self.derived = [None] * self.count
         self._keep = {}

@@ -4,11 +4,13 @@ Both sides start from the same seeded macroscopic fields and build their own
 populations.  The library keeps the post-collision state f*(t); the oracle's
 f*(t) is collide(f(t)).
 
-Bars:
+Bars (the same measures as the benchmark's error report):
   * FP64: max |f*_gpu - f*_oracle| <= 1e-12 max |f*_oracle| (populations),
     rho and T within 1e-12 of the oracle relative to their maxima, u within
     1e-12 (lattice units, cs = 1).
-  * FP32 deviation form: rho, u, T within 1e-5 of the FP64 oracle.
+  * FP32 deviation form: rho, u, T within 1e-5 of the FP64 oracle, max
+    absolute error in lattice units (rho0 = 1, cs^2 ~ 1; the zero of T is the
+    free parameter E0, so a bound relative to max |T| would depend on it).
   * Streaming only (collide = 0, bounce-back / periodic): bit-exact.
 """
 from __future__ import annotations
@@ -885,6 +887,47 @@ def test_batched_workload_full_size_sampled_parity(workload):
         assert_fp32(gm, om)
 
 
+# Cavities of the 64-cavity workload the oracle follows for 10^4 steps: the one
+# whose FP32 error is largest (67^2, Pr 5.0, Ra clamped to 2.1e4 at the largest
+# dT of 1.0), the other small cavities at dT >= 0.5, and a large one at dT = 1.0
+# and Ra 7.3e5.
+C4_ORACLE_DOMAINS = (62, 42, 33, 58, 19, 24)
+_C4_ORACLE = {}
+
+
+@pytest.mark.parametrize("interior", [1, 0])
+def test_cavities64_full_batch_10k_steps_oracle_parity(interior):
+    """The 64-cavity batch (every domain, FP32 deviation form) in the
+    benchmark's three-step 32x16 launches, with and without the interior-tile
+    kernel, in HIP graphs of 120 steps, for 10^4 steps (the horizon of the
+    FP32 bound): the worst-conditioned cavities against the FP64 oracle within
+    1e-5 absolute on rho, u and T (the FP32 measure), and every domain finite."""
+    lbm13 = _lb()
+    import bench
+    specs = bench.cavity_specs()
+    steps = 10000
+    say("cavities64 full batch, three-step 32x16, interior %d, %d steps" % (interior, steps))
+    b = bench.build_batch(specs, lbm13.FP32_DEV)
+    b.set_tile(*bench.BENCH_TILE)
+    b.set_fused_tile(32, 16)
+    b.set_steps_per_launch(3)
+    b.set_interior_kernel(interior)
+    b.use_graph(120)
+    b.step(steps)
+    diags = b.diagnostics()
+    assert all(d["nonfinite"] == 0 and d["rho_min"] > 0 for d in diags)
+    worst = 0.0
+    for i in C4_ORACLE_DOMAINS:
+        if i not in _C4_ORACLE:
+            say("  oracle: domain %d (%dx%d), %d steps" % (i, specs[i]["nx"], specs[i]["ny"], steps))
+            _C4_ORACLE[i] = _oracle_for_spec(specs[i], steps)
+        errs = assert_fp32([t.cpu().numpy() for t in b.moments(i)], _C4_ORACLE[i])
+        say("  domain %d: rho %.2e u %.2e T %.2e" % (i, errs[0], max(errs[1], errs[2]), errs[3]))
+        worst = max(worst, max(errs))
+    say("  worst %.3e" % worst)
+    b.destroy()
+
+
 def test_channel_profiles_match_startup_series():
     """Secs. 7, 8: channels started from rest, FP32 batched form: u_y(x, t) follows
     the Couette / Poiseuille start-up series and T(x, t) the conduction series
@@ -1098,8 +1141,9 @@ def test_transverse_wave_energy_growth_matches_oracle(precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_full_size_wave_rates_match_linear_theory(precision):
-    """4096^2 shear + acoustic wave in the benchmark's launch configuration, 20000
-    steps: the shear mode decays at the eigenvalue of the linear amplification
+    """4096^2 shear + acoustic wave in the benchmark's three-step launch
+    configuration (FP32 64x16, FP64 32x16 tiles), in HIP graphs of 120 steps,
+    20040 steps: the shear mode decays at the eigenvalue of the linear amplification
     matrix (nu k^2 = 1.4707e-7 per step), the sound wave oscillates at its
     eigenfrequency and is damped at its rate, and the initial density wave at
     uniform T splits into sound (28/(28 + B) of it) and the diffusive mode."""
@@ -1113,18 +1157,21 @@ def test_full_size_wave_rates_match_linear_theory(precision):
     lam_s = [m for m in linear.hydro_modes(po, (0, k)) if abs(m[1]) < 1e-9][0][0]
     sound = [m for m in linear.hydro_modes(po, (k, 0)) if m[1] > 1e-6][0]
     B = oracle.derive(po)[1]["B"]
-    cfg = bench.BENCH_CONFIG[precision]
-    say("full-size wave rates precision %d, 20000 steps" % precision)
+    cfg = bench.BENCH_CONFIG[precision]  # the three-step launch the benchmark times
+    say("full-size wave rates precision %d, %s, 20040 steps" % (precision, cfg))
     lat = lbm13.Lattice(n, n, precision)
+    lat.set_tile(*cfg["tile"])
     lat.set_fused_tile(*cfg["fused_tile"])
     lat.set_steps_per_launch(cfg["spl"])
+    lat.set_interior_kernel(cfg["interior_kernel"])
     lat.set_params()
     lat.init_moments(*workloads.shear_acoustic(n))
-    lat.use_graph(100)
+    assert lat.launch_config()["steps_per_launch"] == 3
+    lat.use_graph(120)
     ts, shear, rho = [], [], []
-    for t in range(0, 20001, 100):
+    for t in range(0, 20041, 120):
         if t:
-            lat.step(100)
+            lat.step(120)
         ts.append(t)
         shear.append(lat.fourier(0, 1)["ux"])
         rho.append(lat.fourier(1, 0)["rho"].real)
