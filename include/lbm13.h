@@ -255,6 +255,33 @@ int lbm13_set_fused_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
  * the same arithmetic differently).  EINVAL otherwise. */
 int lbm13_set_interior_kernel(lbm13_ctx *ctx, int on);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): advance one
+ * nx x ny domain by n >= 0 steps without a context or workspace.  f_in: device
+ * array [13][ny][nx] of the absolute FP64 post-collision populations f*(t), as
+ * lbm13_get_state writes them; f_out (device, same layout, may equal f_in)
+ * receives f*(t + n).  p, sides: as lbm13_set_params (host memory, read during
+ * the call).  The result is bit-identical to lbm13_create + lbm13_set_params
+ * + lbm13_set_state(f_in) + lbm13_step(n) + lbm13_get_state(f_out) with the
+ * default tiles, three steps per launch and the interior-tile kernel off (the
+ * same kernels).  Every other buffer (working-precision populations, tile
+ * tables, parameter block, wall side arrays) lives in one static device array
+ * of LBM13_NOALLOC_SCRATCH_BYTES (64 MiB) per device, which each device that
+ * runs the call holds until the process ends: the call allocates no device or
+ * pinned memory, creates no stream or event, does not synchronise and enqueues
+ * only kernels on `stream` (hipStream_t, NULL = the null stream), so it can be
+ * captured.  The array keeps the last call's contents and is shared by every
+ * call on the device: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.  Errors (the message in
+ * lbm13_last_error(NULL)): EINVAL for NULL pointers, n < 0, bad sizes or sides,
+ * or a domain whose buffers exceed the array (the limit is
+ * lbm13_workspace_bytes(nx, ny, precision) <= LBM13_NOALLOC_SCRATCH_BYTES:
+ * squares up to 768^2 in FP32_DEV and 556^2 in FP64), all before any device
+ * work; EUNSTABLE_PARAMS as lbm13_derive; EDEVICE.  Async. */
+#define LBM13_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lbm13_advance_noalloc(int nx, int ny, int precision, const lbm13_params *p, const lbm13_side sides[4],
+                          const double *f_in, double *f_out, long long n, void *stream);
+
 /* Destroy the context: waits for the work queued on its stream (graph
  * replays included), then frees its host objects, graphs, auxiliary streams and
  * events; never the workspace, which the caller may free once this returns. */

@@ -48,6 +48,8 @@ hipError_t launch_get_state(int, int, const R*, const Dom<R>*, int, double*, hip
 template <typename R>
 hipError_t launch_set_state(int, int, R*, const Dom<R>*, int, const double*, hipStream_t);
 hipError_t launch_ckpt_header(const CkptHeader&, void*, hipStream_t);
+hipError_t launch_upload(const void*, size_t, void*, hipStream_t);
+hipError_t noalloc_scratch(void**);
 }  // namespace lbm13
 
 using lbm13::Dom;
@@ -229,6 +231,7 @@ struct lbm13_batch {
     int tile_x = 64, tile_y = 8;
     int cur = 0;                          // buffer holding the current state
     char* bufp[2] = {nullptr, nullptr};   // the two population buffers
+    bool noalloc = false;                 // workspace is the static scratch: uploads by kernel arguments, no syncs
     long long steps = 0;
     int graph_k = 0;
     int graph_flip = 0;                   // 1 when a captured graph has an odd number of launches
@@ -269,11 +272,13 @@ R* buf(lbm13_batch* b, int which) {
     return reinterpret_cast<R*>(b->bufp[which]);
 }
 
-// Host data to the workspace at byte offset `off` (an async copy: the host
-// data must live until it runs; the callers keep it in the batch and
-// synchronise).
+// Host data to the workspace at byte offset `off`: an async copy (the host
+// data must live until it runs: the callers keep it in the batch and
+// synchronise), or, for the allocation-free path, kernel launches that carry
+// the data as arguments (nothing to keep, capture-safe).
 hipError_t upload(lbm13_batch* b, size_t off, const void* host, size_t bytes) {
     if (bytes == 0) return hipSuccess;
+    if (b->noalloc) return lbm13::launch_upload(host, bytes, b->ws + off, b->stream);
     return hipMemcpyAsync(b->ws + off, host, bytes, hipMemcpyHostToDevice, b->stream);
 }
 
@@ -431,8 +436,10 @@ int rebuild(lbm13_batch* b) {
     if (e != hipSuccess) return hip_fail(b, e, "upload wall lines");
     e = upload(b, b->L.doms, b->dom_host.data(), b->dom_host.size());
     if (e != hipSuccess) return hip_fail(b, e, "upload domain table");
-    e = hipStreamSynchronize(b->stream);  // the async copies read the host tables
-    if (e != hipSuccess) return hip_fail(b, e, "synchronise");
+    if (!b->noalloc) {  // the async copies read the host tables: keep them until done
+        e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(b, e, "synchronise");
+    }
     drop_graphs(b);
     return LBM13_OK;
 }
@@ -752,6 +759,38 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
 }  // namespace
 
 // =========================================================================== batch API
+
+namespace {
+
+// The allocation-free step: a batch of one domain whose workspace is the
+// static device scratch (tables uploaded as kernel arguments, no
+// synchronisation), state in from f_in, n steps of the context path with
+// three steps per launch and the interior kernel off, state out to f_out.
+template <typename R>
+int advance_noalloc_impl(lbm13_batch& b, const lbm13_params* p, const lbm13_side sides[4],
+                                const lbm13_derived& dv, const double* f_in, double* f_out, long long n) {
+    fill_dom<R>(&b, 0, p, sides, &dv);
+    b.has_params[0] = 1;
+    int st = rebuild(&b);
+    if (st) return st;
+    hipError_t e = lbm13::launch_set_state<R>(b.nx[0], b.ny[0], buf<R>(&b, b.cur), doms_dev<R>(&b), 0, f_in, b.stream);
+    if (e != hipSuccess) return hip_fail(&b, e, "set_state launch");
+    e = fill_side<R>(&b, 0);
+    if (e != hipSuccess) return hip_fail(&b, e, "side fill launch");
+    b.has_state[0] = 1;
+    st = step_impl<R>(&b, n);
+    if (st) return st;
+    e = lbm13::launch_get_state<R>(b.nx[0], b.ny[0], buf<R>(&b, b.cur), doms_dev<R>(&b), 0, f_out, b.stream);
+    if (e != hipSuccess) return hip_fail(&b, e, "get_state launch");
+    return LBM13_OK;
+}
+
+int noalloc_fail(int code, const std::string& msg) {
+    g_create_err = "lbm13_advance_noalloc: " + msg;
+    return code;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1205,6 +1244,54 @@ int lbm13_destroy(lbm13_ctx* c) {
     int st = lbm13_batch_destroy(c->b);
     delete c;
     return st;
+}
+
+int lbm13_advance_noalloc(int nx, int ny, int precision, const lbm13_params* p, const lbm13_side sides[4],
+                          const double* f_in, double* f_out, long long n, void* stream) {
+    if (!p || !sides || !f_in || !f_out || n < 0) return noalloc_fail(LBM13_EINVAL, "bad argument");
+    Layout L;
+    if (!make_layout(1, &nx, &ny, precision, L)) return noalloc_fail(LBM13_EINVAL, "invalid size or precision");
+    if (L.total > lbm13::kNoallocScratchBytes)
+        return noalloc_fail(LBM13_EINVAL, "a " + std::to_string(nx) + " x " + std::to_string(ny) + " domain needs " +
+                                              std::to_string(L.total) + " bytes; the static scratch holds " +
+                                              std::to_string(lbm13::kNoallocScratchBytes));
+    for (int w = 0; w < 4; ++w)
+        if (sides[w].kind < LBM13_PERIODIC || sides[w].kind > LBM13_WALL_DIRICHLET_T)
+            return noalloc_fail(LBM13_EINVAL, "unknown side kind");
+    if ((sides[0].kind == LBM13_PERIODIC) != (sides[1].kind == LBM13_PERIODIC) ||
+        (sides[2].kind == LBM13_PERIODIC) != (sides[3].kind == LBM13_PERIODIC))
+        return noalloc_fail(LBM13_EINVAL, "opposite sides must both be periodic or both walls");
+    lbm13_derived dv;
+    if (derive(p, &dv) != LBM13_OK)
+        return noalloc_fail(LBM13_EUNSTABLE_PARAMS, "relaxation rate outside (0, 2) or degenerate constants");
+    void* sp = nullptr;
+    hipError_t e = lbm13::noalloc_scratch(&sp);
+    if (e != hipSuccess) return noalloc_fail(LBM13_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    lbm13_batch b;
+    b.count = 1;
+    b.precision = precision;
+    b.nx.assign(1, nx);
+    b.ny.assign(1, ny);
+    b.L = L;
+    b.ws = static_cast<char*>(sp);
+    b.bufp[0] = b.ws + L.bufA;
+    b.bufp[1] = b.ws + L.bufB;
+    b.noalloc = true;
+    b.stream = static_cast<hipStream_t>(stream);
+    b.dom_host.assign(dom_size(&b), 0);
+    b.coef_host.assign(kCoef, 0.0);
+    b.sides_kind.assign(4, LBM13_PERIODIC);
+    for (int w = 0; w < 4; ++w) b.sides_kind[w] = sides[w].kind;
+    b.has_params.assign(1, 0);
+    b.has_state.assign(1, 0);
+    b.ftw = precision == LBM13_FP64 ? lbm13::Fused<double>::TW : lbm13::Fused<float>::TW;
+    b.fth = precision == LBM13_FP64 ? lbm13::Fused<double>::TH : lbm13::Fused<float>::TH;
+    b.split = 0;
+    b.spl = 3;
+    const int st = precision == LBM13_FP64 ? advance_noalloc_impl<double>(b, p, sides, dv, f_in, f_out, n)
+                                           : advance_noalloc_impl<float>(b, p, sides, dv, f_in, f_out, n);
+    if (st) return noalloc_fail(st, b.err);
+    return LBM13_OK;
 }
 
 const char* lbm13_last_error(const lbm13_ctx* c) {

@@ -104,6 +104,19 @@ struct CkptHeader {
 constexpr int kCkptVersion = 1;
 constexpr size_t kCkptHeaderBytes = 256;
 
+// Size of the static device array that the allocation-free entry point
+// (lbm13_advance_noalloc) keeps its buffers in, per device.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+
+// Host data handed to a kernel by value (kernel arguments are copied at
+// launch and into a captured graph), for uploads that must not depend on host
+// memory outliving the call: kUploadWords 32-bit words per launch.
+constexpr int kUploadWords = 768;
+struct UploadChunk {
+    unsigned int words;
+    unsigned int w[kUploadWords];
+};
+
 constexpr int kDiagPartials = 10;  // per-tile partial reductions
 constexpr int kDiagOut = 16;       // values per domain
 

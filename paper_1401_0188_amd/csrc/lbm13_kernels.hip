@@ -16,6 +16,10 @@
 // intermediate states in LDS, so HBM is read and written once per launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "lbm13_device.h"
@@ -1629,6 +1633,59 @@ hipError_t launch_set_state(int nx, int ny, R* dst, const Dom<R>* doms, int d, c
     const dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
     set_state_kernel<R><<<grd, blk, 0, s>>>(dst, doms, d, in);
     return hipGetLastError();
+}
+
+// Copies one chunk of host data, passed by value, to dst (4-byte aligned).
+__global__ __launch_bounds__(256) void upload_kernel(UploadChunk c, unsigned int* __restrict__ dst) {
+    for (unsigned int i = threadIdx.x; i < c.words; i += 256) dst[i] = c.w[i];
+}
+
+// Uploads `bytes` (a multiple of 4) of host data to device address dst as a
+// sequence of upload_kernel launches on s.  Returns once the arguments are
+// copied, so the host data may change or be freed right after; safe under
+// stream capture (each launch is recorded with its arguments).
+hipError_t launch_upload(const void* host, size_t bytes, void* dst, hipStream_t s) {
+    if (bytes % 4 != 0 || reinterpret_cast<uintptr_t>(dst) % 4 != 0) return hipErrorInvalidValue;
+    const unsigned char* src = static_cast<const unsigned char*>(host);
+    unsigned char* out = static_cast<unsigned char*>(dst);
+    UploadChunk c;
+    for (size_t off = 0; off < bytes; off += 4 * (size_t)kUploadWords) {
+        const size_t n = std::min(bytes - off, 4 * (size_t)kUploadWords);
+        c.words = (unsigned int)(n / 4);
+        std::memcpy(c.w, src + off, n);
+        upload_kernel<<<1, 256, 0, s>>>(c, reinterpret_cast<unsigned int*>(out + off));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// The allocation-free entry point's buffers: one array per device, held until
+// the process ends.  Host code must not use the name `scratch` as an address
+// (on the host it is a stand-in, not device memory); it takes the device
+// address from noalloc_scratch().
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+// Device address of `scratch` on the current device, taken once per device
+// (with that device current) by hipGetSymbolAddress and kept.
+hipError_t noalloc_scratch(void** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 // Writes a checkpoint header (passed by value, so the launch owns its copy).

@@ -105,6 +105,7 @@ def lib():
         "lbm13_launch_config": (i32, [vp, ip]),
         "lbm13_destroy": (i32, [vp]),
         "lbm13_last_error": (ctypes.c_char_p, [vp]),
+        "lbm13_advance_noalloc": (i32, [i32, i32, i32, P, S, dp, dp, i64, vp]),
         "lbm13_batch_workspace_bytes": (sz, [i32, ip, ip, i32]),
         "lbm13_batch_create": (i32, [i32, ip, ip, i32, vp, sz, vp, ctypes.POINTER(vp)]),
         "lbm13_batch_set_params": (i32, [vp, i32, P, S, D]),
@@ -161,6 +162,30 @@ def make_sides(kinds=(PERIODIC,) * 4, u_t=(0.0,) * 4, T_w=(0.0,) * 4):
         arr[w].u_tangential = float(u_t[w])
         arr[w].T_wall = float(T_w[w])
     return arr
+
+
+def advance_noalloc(nx: int, ny: int, precision: int, f_in, n: int, sides=None, f_out=None, stream=None, **kw):
+    """lbm13_advance_noalloc: n steps of one domain from the absolute FP64
+    post-collision populations f_in (device tensor [13][ny][nx]) into f_out
+    (a new tensor unless given; may be f_in), with no context, no workspace
+    and no device allocation inside the library (buffers in its static
+    scratch).  Calls that overlap on one device race.  Returns f_out."""
+    torch = _torch()
+    f_in = _dev_f64(f_in, torch, 13 * int(nx) * int(ny))
+    if f_out is None:
+        f_out = torch.empty_like(f_in)
+    elif not (f_out.is_cuda and f_out.is_contiguous() and f_out.dtype == torch.float64
+              and f_out.numel() == f_in.numel()):
+        raise LBM13Error(EINVAL, "f_out must be a contiguous float64 device tensor of 13*nx*ny values")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib().lbm13_advance_noalloc(int(nx), int(ny), int(precision), ctypes.byref(make_params(**kw)),
+                                     sides if sides is not None else make_sides(), ctypes.c_void_p(f_in.data_ptr()),
+                                     ctypes.c_void_p(f_out.data_ptr()), int(n), ctypes.c_void_p(s.cuda_stream))
+    if st != OK:
+        raise LBM13Error(st, (lib().lbm13_last_error(None) or b"").decode())
+    f_in.record_stream(s)
+    f_out.record_stream(s)
+    return f_out
 
 
 def derive(**kw):
