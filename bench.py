@@ -181,18 +181,20 @@ def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0
 def cavity_specs(count=64, seed=4):
     """Heated cavities of uneven sizes (side U{64..512}), Ra log-uniform in
     [1e3, 1e6], Pr U[0.5, 7] (one seeded draw per cavity), each with its own
-    parameter set and feasible forcing (Ra clamped and recorded when needed)."""
+    parameter set and feasible forcing (dT within the cap of
+    workloads.cavity_dT_cap; Ra clamped and recorded when needed)."""
     from paper_1401_0188_amd import lbm13, workloads
     out = []
     for i, c in enumerate(workloads.cavity_batch(count=count, seed=seed)):
         kw = workloads.cavity_parameter_set(c["Pr"])
         st, d = lbm13.derive(**kw)
-        cf = workloads.cavity_forcing(c["nx"], c["Ra"], c["Pr"], d["nu"], d["kappa"])
+        cf = workloads.cavity_forcing(c["nx"], c["Ra"], c["Pr"], d["nu"], d["kappa"],
+                                      dT_max=workloads.cavity_dT_cap(c["nx"]))
         E0 = kw["E0"]
         out.append(dict(nx=c["nx"], ny=c["ny"], kw=dict(kw, g=(0.0, -cf["g"])),
                         sides=((2, 2, 1, 1), (0, 0, 0, 0), (E0 + cf["dT"] / 2, E0 - cf["dT"] / 2, 0, 0)),
                         fields=("cavity", dict(n=c["nx"], T0=E0, dT=cf["dT"], seed=seed * 1000 + i)),
-                        info=dict(Pr=c["Pr"], Ra=c["Ra"], Ra_eff=cf["Ra"], clamped=cf["clamped"])))
+                        info=dict(Pr=c["Pr"], Ra=c["Ra"], Ra_eff=cf["Ra"], clamped=cf["clamped"], dT=cf["dT"])))
     return out
 
 
