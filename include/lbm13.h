@@ -212,6 +212,18 @@ int lbm13_set_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
  * lbm13_launch_config for the whole choice).  Synchronises. */
 int lbm13_autotune(lbm13_ctx *ctx, int steps, int *tile_x, int *tile_y);
 
+/* lbm13_autotune through a cache file (host path; created if missing): the
+ * launch configuration tuned earlier for the same device architecture,
+ * precision and size class (floor(log2) of the node count and of the domain
+ * count, walls present or not) is applied without timing, else the autotuner
+ * runs and its choice is stored.  The file is JSON, {"version": 1, "entries":
+ * {key: [the six integers of lbm13_launch_config]}}; damaged content or an
+ * entry this build does not support is ignored and tuned again.  *from_cache
+ * (may be NULL) tells which happened.  A cache that cannot be written leaves
+ * the tuned configuration in place, returns LBM13_OK and says so in
+ * lbm13_last_error.  Synchronises when it tunes. */
+int lbm13_autotune_cached(lbm13_ctx *ctx, int steps, const char *cache_path, int *from_cache);
+
 /* Current launch configuration: cfg = {steps per launch, single-step tile_x,
  * tile_y, two- and three-step tile_x, tile_y, interior kernel on (1) or off
  * (0)}.
@@ -319,6 +331,7 @@ int lbm13_batch_save(lbm13_batch *b, int i, void *dst, size_t dst_bytes);
 int lbm13_batch_load(lbm13_batch *b, int i, const void *src, size_t src_bytes);
 int lbm13_batch_set_tile(lbm13_batch *b, int tile_x, int tile_y);
 int lbm13_batch_autotune(lbm13_batch *b, int steps, int *tile_x, int *tile_y);
+int lbm13_batch_autotune_cached(lbm13_batch *b, int steps, const char *cache_path, int *from_cache);
 int lbm13_batch_use_graph(lbm13_batch *b, int k);
 int lbm13_batch_set_steps_per_launch(lbm13_batch *b, int k);
 int lbm13_batch_set_fused_tile(lbm13_batch *b, int tile_x, int tile_y);

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm13.so")
-SOURCES = [os.path.join(CSRC, "lbm13_kernels.hip"), os.path.join(CSRC, "lbm13_capi.cpp")]
+SOURCES = [os.path.join(CSRC, "lbm13_kernels.hip"), os.path.join(CSRC, "lbm13_capi.cpp"),
+           os.path.join(CSRC, "lbm13_tune_cache.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no packed FP32 VALU instructions are generated.

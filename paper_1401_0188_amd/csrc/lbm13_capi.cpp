@@ -17,6 +17,7 @@
 
 #include "../../include/lbm13.h"
 #include "lbm13_device.h"
+#include "lbm13_tune_cache.h"
 
 #ifndef LBM13_PLANE_PAD
 #define LBM13_PLANE_PAD 256  // elements added to each velocity plane (breaks power-of-two plane strides)
@@ -1084,6 +1085,47 @@ int lbm13_batch_autotune(lbm13_batch* b, int steps, int* tile_x, int* tile_y) {
                                       : autotune_impl<float>(b, steps, tile_x, tile_y);
 }
 
+int lbm13_batch_autotune_cached(lbm13_batch* b, int steps, const char* cache_path, int* from_cache) {
+    if (from_cache) *from_cache = 0;
+    if (!b || steps <= 0 || !cache_path) return b ? fail(b, LBM13_EINVAL, "bad argument") : LBM13_EINVAL;
+    int st = ready(b);
+    if (st) return st;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(b, e, "device properties");
+    bool walls = false;
+    for (int k : b->sides_kind) walls = walls || k != LBM13_PERIODIC;
+    const std::string key = lbm13::tune_key(prop.gcnArchName, b->precision, lbm13_batch_nodes(b), b->count, walls);
+    int cfg[6];
+    if (lbm13::tune_cache_lookup(cache_path, key, cfg)) {
+        // accept only a configuration this build supports for this precision
+        bool ok = cfg[0] >= 1 && cfg[0] <= 3 && valid_shape(cfg[1], cfg[2]) && (cfg[5] == 0 || cfg[5] == 1);
+        bool fused = false;
+        for (auto& f : kFusedShapes) fused = fused || (f[0] == cfg[3] && f[1] == cfg[4]);
+        ok = ok && fused && fused_fits(b->precision, cfg[3], cfg[4]);
+        if (ok && cfg[0] == 3) ok = step3_shape(b->precision, cfg[3], cfg[4]);
+        if (ok) {
+            b->spl = cfg[0];
+            b->tile_x = cfg[1];
+            b->tile_y = cfg[2];
+            b->ftw = cfg[3];
+            b->fth = cfg[4];
+            b->split = cfg[5];
+            st = rebuild(b);
+            if (st) return st;
+            if (from_cache) *from_cache = 1;
+            return LBM13_OK;
+        }
+    }
+    st = lbm13_batch_autotune(b, steps, nullptr, nullptr);
+    if (st) return st;
+    (void)lbm13_batch_launch_config(b, cfg);
+    if (!lbm13::tune_cache_store(cache_path, key, cfg)) b->err = "autotuned; the cache file could not be written";
+    return LBM13_OK;
+}
+
 int lbm13_batch_use_graph(lbm13_batch* b, int k) {
     if (!b) return LBM13_EINVAL;
     if (k != 0 && (k < 2 || k > 4096 || (k & 1))) return fail(b, LBM13_EINVAL, "graph length must be even, 2..4096");
@@ -1221,6 +1263,10 @@ int lbm13_set_tile(lbm13_ctx* c, int tile_x, int tile_y) {
 
 int lbm13_autotune(lbm13_ctx* c, int steps, int* tile_x, int* tile_y) {
     return c ? lbm13_batch_autotune(c->b, steps, tile_x, tile_y) : LBM13_EINVAL;
+}
+
+int lbm13_autotune_cached(lbm13_ctx* c, int steps, const char* cache_path, int* from_cache) {
+    return c ? lbm13_batch_autotune_cached(c->b, steps, cache_path, from_cache) : LBM13_EINVAL;
 }
 
 int lbm13_use_graph(lbm13_ctx* c, int k) { return c ? lbm13_batch_use_graph(c->b, k) : LBM13_EINVAL; }

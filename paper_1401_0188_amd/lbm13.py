@@ -98,6 +98,7 @@ def lib():
         "lbm13_load": (i32, [vp, vp, sz]),
         "lbm13_set_tile": (i32, [vp, i32, i32]),
         "lbm13_autotune": (i32, [vp, i32, ip, ip]),
+        "lbm13_autotune_cached": (i32, [vp, i32, ctypes.c_char_p, ip]),
         "lbm13_use_graph": (i32, [vp, i32]),
         "lbm13_set_steps_per_launch": (i32, [vp, i32]),
         "lbm13_set_fused_tile": (i32, [vp, i32, i32]),
@@ -121,6 +122,7 @@ def lib():
         "lbm13_batch_load": (i32, [vp, i32, vp, sz]),
         "lbm13_batch_set_tile": (i32, [vp, i32, i32]),
         "lbm13_batch_autotune": (i32, [vp, i32, ip, ip]),
+        "lbm13_batch_autotune_cached": (i32, [vp, i32, ctypes.c_char_p, ip]),
         "lbm13_batch_use_graph": (i32, [vp, i32]),
         "lbm13_batch_set_steps_per_launch": (i32, [vp, i32]),
         "lbm13_batch_set_fused_tile": (i32, [vp, i32, i32]),
@@ -376,6 +378,12 @@ class Lattice(_Base):
         self._check(lib().lbm13_autotune(self._h, int(steps), ctypes.byref(tx), ctypes.byref(ty)))
         return tx.value, ty.value
 
+    def autotune_cached(self, cache_path: str, steps: int = 20) -> bool:
+        """Autotune through the cache file; True when the cached choice was applied."""
+        hit = ctypes.c_int()
+        self._check(lib().lbm13_autotune_cached(self._h, int(steps), os.fsencode(cache_path), ctypes.byref(hit)))
+        return bool(hit.value)
+
     def use_graph(self, k: int):
         self._check(lib().lbm13_use_graph(self._h, int(k)))
 
@@ -503,6 +511,13 @@ class Batch(_Base):
         tx, ty = ctypes.c_int(), ctypes.c_int()
         self._check(lib().lbm13_batch_autotune(self._h, int(steps), ctypes.byref(tx), ctypes.byref(ty)))
         return tx.value, ty.value
+
+    def autotune_cached(self, cache_path: str, steps: int = 20) -> bool:
+        """Autotune through the cache file; True when the cached choice was applied."""
+        hit = ctypes.c_int()
+        self._check(lib().lbm13_batch_autotune_cached(self._h, int(steps), os.fsencode(cache_path),
+                                                       ctypes.byref(hit)))
+        return bool(hit.value)
 
     def use_graph(self, k: int):
         self._check(lib().lbm13_batch_use_graph(self._h, int(k)))

@@ -799,6 +799,40 @@ def test_checkpoint_load_rejects_foreign_blobs():
     b.destroy()
 
 
+def test_autotune_cache_round_trip(tmp_path):
+    """lbm13_autotune_cached: the first call tunes and stores its choice, a
+    second context of the same size class applies it without timing, a
+    damaged cache file is tuned again and rewritten as valid JSON."""
+    import json
+    lbm13 = _lb()
+    say("autotune cache")
+    path = str(tmp_path / "tune.json")
+    fields = workloads.shear_acoustic(96, 64)
+
+    def ctx():
+        lat = lbm13.Lattice(96, 64, lbm13.FP32_DEV)
+        lat.set_params()
+        lat.init_moments(*fields)
+        return lat
+    a = ctx()
+    assert a.autotune_cached(path, steps=6) is False
+    cfg = a.launch_config()
+    entries = json.load(open(path))["entries"]
+    assert len(entries) == 1 and list(entries.values())[0][0] == cfg["steps_per_launch"]
+    b = ctx()
+    assert b.autotune_cached(path, steps=6) is True
+    assert b.launch_config() == cfg
+    with open(path, "w") as fh:
+        fh.write('{"version": 1, "entries": {"%s": [3, 64' % list(entries)[0])
+    c = ctx()
+    assert c.autotune_cached(path, steps=6) is False
+    assert json.load(open(path))["entries"]
+    c.step(6)
+    assert c.diagnostics()["nonfinite"] == 0
+    for lat in (a, b, c):
+        lat.destroy()
+
+
 def test_error_paths():
     lbm13 = _lb()
     say("error paths")
