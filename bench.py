@@ -609,15 +609,17 @@ def small_cases(workload):
                      kinds=(0, 0, 0, 0), T_w=(0, 0, 0, 0), kw={}, label="wave",
                      desc="periodic 32x32 nonlinear wave (rho, ux cosine)")]
     from paper_1401_0188_amd import lbm13
-    n, Pr, s_XX = 256, 0.71, 1.7
-    st, d = lbm13.derive(Pr=Pr, s_XX=s_XX)
+    n = 256
+    kw0 = dict(workloads.CAVITY_PR071_SET)
+    Pr, E0 = kw0["Pr"], kw0["E0"]
+    st, d = lbm13.derive(**kw0)
     out = []
     for Ra in CAVITY_RA:
-        cf = workloads.cavity_forcing(n, Ra, Pr, d["nu"], d["kappa"])
+        cf = workloads.cavity_forcing(n, Ra, Pr, d["nu"], d["kappa"], cs=d["cs2"] ** 0.5)
         out.append(dict(n=n, steps=100000, check_steps=10000, forms=(0, 1),
-                        fields=workloads.cavity_fields(n, seed=0, dT=cf["dT"]), kinds=(2, 2, 1, 1),
-                        T_w=(-2 + cf["dT"] / 2, -2 - cf["dT"] / 2, 0, 0),
-                        kw=dict(Pr=Pr, s_XX=s_XX, g=(0.0, -cf["g"])), label="Ra %.0e" % Ra,
+                        fields=workloads.cavity_fields(n, T0=E0, seed=0, dT=cf["dT"]), kinds=(2, 2, 1, 1),
+                        T_w=(E0 + cf["dT"] / 2, E0 - cf["dT"] / 2, 0, 0),
+                        kw=dict(kw0, g=(0.0, -cf["g"])), label="Ra %.0e" % Ra,
                         Ra=cf["Ra"], dT=cf["dT"], g=cf["g"],
                         desc="heated cavity 256x256, Ra 1e3, 1e4, 1e5, Pr 0.71, hot West / cold East, adiabatic S/N"))
     return out

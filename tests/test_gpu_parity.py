@@ -166,16 +166,18 @@ _CAVITY_ORACLE = {}
 
 def _cavity_256(Ra):
     """The 256^2 heated cavity at Rayleigh number Ra (sec. 10 geometry: hot West,
-    cold East, adiabatic South and North walls, Pr = 0.71) and its oracle run of
-    10^4 steps, computed once per Ra."""
+    cold East, adiabatic South and North walls, Pr = 0.71, the cavity parameter
+    set at s_XX = 1.9) and its oracle run of 10^4 steps, computed once per Ra."""
     if Ra not in _CAVITY_ORACLE:
-        n, Pr, s_XX = 256, 0.71, 1.7
-        st, d = oracle.derive(oracle.params(Pr=Pr, s_XX=s_XX))
-        cf = workloads.cavity_forcing(n, Ra, Pr, d["nu"], d["kappa"])
+        n = 256
+        kw0 = dict(workloads.CAVITY_PR071_SET)
+        E0 = kw0["E0"]
+        st, d = oracle.derive(oracle.params(**kw0))
+        cf = workloads.cavity_forcing(n, Ra, kw0["Pr"], d["nu"], d["kappa"], cs=d["cs2"] ** 0.5)
         dT = cf["dT"]
-        fields = workloads.cavity_fields(n, seed=0, dT=dT)
-        T_w = (-2 + dT / 2, -2 - dT / 2, 0, 0)
-        kw = dict(Pr=Pr, s_XX=s_XX, g=(0.0, -cf["g"]))
+        fields = workloads.cavity_fields(n, T0=E0, seed=0, dT=dT)
+        T_w = (E0 + dT / 2, E0 - dT / 2, 0, 0)
+        kw = dict(kw0, g=(0.0, -cf["g"]))
         po, _ = params_pair(**dict(kw))
         so = oracle.sides((2, 2, 1, 1), (0, 0, 0, 0), T_w)
         f = oracle.run(oracle.init(*fields, po), po, so, 10000)

@@ -596,6 +596,25 @@ def test_cavity_parameter_sets_are_linearly_stable(Pr):
             assert w <= 1 + 1e-9, (dE, U, w)
 
 
+def test_cavity_pr071_set_is_linearly_stable():
+    """The 256^2 heated cavity's parameter set (Pr = 0.71, s_XX = 1.9, nu =
+    0.0144) keeps every linear mode bounded at rest, with |u| up to 0.07 along
+    x, y and the diagonal, and with energy offsets of +-0.1 (its cavities use
+    dT <= 0.06 at Ra <= 1e5)."""
+    kw = dict(workloads.CAVITY_PR071_SET)
+    p = oracle.params(**kw)
+    st, d = oracle.derive(p)
+    assert st == 0 and d["nu"] == pytest.approx(0.01443, rel=1e-3)
+    for dE in (0.0, -0.1, 0.1):
+        for U in ((0.0, 0.0), (0.05, 0.0), (0.0, 0.05), (0.035, 0.035), (0.07, 0.0)):
+            w = 0.0
+            for kx in np.linspace(0, np.pi, 17):
+                for ky in np.linspace(0, kx, 17):
+                    A = linear.amplification(p, (kx, ky), U, rho=1 - dE / 28, E=p.E0 + dE)
+                    w = max(w, float(np.abs(np.linalg.eigvals(A)).max()))
+            assert w <= 1 + 1e-9, (dE, U, w)
+
+
 @pytest.mark.parametrize("kind,W,U,F", [("couette", 32, 0.01, 0.0), ("poiseuille", 40, 0.0, 1e-6)])
 def test_channel_startup_follows_series(kind, W, U, F):
     """Channels started from rest: u_y(x, t) follows the Couette / Poiseuille
