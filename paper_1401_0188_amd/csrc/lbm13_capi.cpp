@@ -495,6 +495,14 @@ void fill_dom(lbm13_batch* b, int d, const lbm13_params* p, const lbm13_side* si
     D->kXe = R(p->s_XXe / 68.0);
     D->kq = R(dv->s_q / 20.0);
     D->kr = R(p->s_rx / 70.0);
+    {
+        // update patterns of an axis' odd populations from the relaxations
+        // kq (q - q^eq) and kr (r - r^eq): speed-1 -2, 4; speed-2 2, 1;
+        // diagonal -1, -3 (rows of M^T D^-1 over q and r)
+        const double kq = dv->s_q / 20.0, kr = p->s_rx / 70.0;
+        const double w[6] = {-2.0 * kq, 4.0 * kr, 2.0 * kq, kr, -kq, -3.0 * kr};
+        for (int k = 0; k < 6; ++k) D->ow[k] = R(w[k]);
+    }
     D->fjx = R(-F0x / 14.0);
     D->fjy = R(-F0y / 14.0);
     D->gjx = R(-p->g[0] / 14.0);

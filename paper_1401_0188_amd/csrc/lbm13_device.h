@@ -42,6 +42,10 @@ struct alignas(16) Dom {
     //   -F / 14 = fjx + gjx rho' (and y) for the body force F = F0 + g (rho - rho0)
     R aeps[4], avp[4];
     R eQ[4];
+    // odd moments: per axis, the update patterns of the speed-1 link, the
+    // speed-2 link and the diagonal are ow[2c] nq + ow[2c+1] nr (c = 0, 1, 2),
+    // nq = q - q^eq, nr = r - r^eq: ow = (-2 kq, 4 kr, 2 kq, kr, -kq, -3 kr)
+    R ow[6];
     R kX, kY, kXe, kq, kr;
     R fjx, fjy, gjx, gjy;
     // walls: tangential velocity, E_W - E0 for temperature walls

@@ -84,23 +84,30 @@ __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
     const R XX = A1 + R(4) * A3;
     const R XY = s57 - s68;
     const R XXe = R(-4) * A1 + A3;
-    const R jx = d13 + d57 - d68 + R(2) * d9;
-    const R jy = d24 + d57 + d68 + R(2) * d10;
-    const R qx = R(-2) * d13 - d57 + d68 + R(2) * d9;
-    const R qy = R(-2) * d24 - d57 - d68 + R(2) * d10;
-    const R rx = R(4) * d13 - R(3) * d57 + R(3) * d68 + d9;
-    const R ry = R(4) * d24 - R(3) * d57 - R(3) * d68 + d10;
+    const R p = d57 - d68, m = d57 + d68;  // diagonal pair differences along x and along y
+    const R jx = (d13 + p) + R(2) * d9;
+    const R jy = (d24 + m) + R(2) * d10;
 
     const R inv_rho = reciprocal(R(1) + rho);
-    const R fq = D.a1 + D.h1 * rho + D.k1 * E;
-    const R fr = D.a2 + D.h2 * rho + D.k2 * E;
     // Delta_k / D_k for the anisotropic even moments
     const R aXX = D.kX * (XX - (jx * jx - jy * jy) * inv_rho);
     const R aXY = D.kY * (XY - jx * jy * inv_rho);
     const R aXXe = D.kXe * XXe;
-    // odd moments
-    const R bqx = D.kq * (qx - jx * fq), bqy = D.kq * (qy - jy * fq);
-    const R brx = D.kr * (rx - jx * fr), bry = D.kr * (ry - jy * fr);
+
+    // odd moments: non-equilibrium parts of q and r per axis (q^eq, r^eq = j
+    // times affine functions of rho and E), mapped onto the three update
+    // patterns of the axis (speed-1 link, speed-2 link, diagonal) by weights
+    // that fold s_q, s_r and the norms: D.ow = (-2, 4; 2, 1; -1, -3) x (kq, kr)
+    const R fq = D.a1 + D.h1 * rho + D.k1 * E;
+    const R fr = D.a2 + D.h2 * rho + D.k2 * E;
+    const R nqx = (R(2) * (d9 - d13) - p) - jx * fq, nrx = (R(4) * d13 + d9 - R(3) * p) - jx * fr;
+    const R nqy = (R(2) * (d10 - d24) - m) - jy * fq, nry = (R(4) * d24 + d10 - R(3) * m) - jy * fr;
+    R o1 = D.ow[0] * nqx + D.ow[1] * nrx;
+    R o9 = D.ow[2] * nqx + D.ow[3] * nrx;
+    R odx = D.ow[4] * nqx + D.ow[5] * nrx;
+    R o2 = D.ow[0] * nqy + D.ow[1] * nry;
+    R o10 = D.ow[2] * nqy + D.ow[3] * nry;
+    R ody = D.ow[4] * nqy + D.ow[5] * nry;
 
     // isotropic even part: eps and varpi relaxed (each a linear form of the
     // class sums), mapped back by the integer rows of M so that the update
@@ -111,7 +118,6 @@ __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
     R ec1 = R(-2) * aeps + R(8) * avp;
     R ec5 = R(-67) * aeps - R(6) * avp;
     R ec9 = R(34) * aeps + avp;
-    R o1, o2, o5, o6, o9, o10;
     if constexpr (Sourced) {
         // the energy source enters as Delta_E = -Q_E (sec. 9), the force as
         // Delta_j = -F (secs. 5, 8)
@@ -120,26 +126,21 @@ __device__ __forceinline__ void collide(R g[13], const Dom<R>& D) {
         ec5 += D.eQ[2];
         ec9 += D.eQ[3];
         const R bjx = D.fjx + D.gjx * rho, bjy = D.fjy + D.gjy * rho;
-        o1 = bjx - R(2) * bqx + R(4) * brx;
-        o2 = bjy - R(2) * bqy + R(4) * bry;
-        o5 = bjx + bjy - bqx - bqy - R(3) * (brx + bry);
-        o6 = -bjx + bjy + bqx - bqy + R(3) * (brx - bry);
-        o9 = R(2) * (bjx + bqx) + brx;
-        o10 = R(2) * (bjy + bqy) + bry;
-    } else {
-        o1 = R(4) * brx - R(2) * bqx;
-        o2 = R(4) * bry - R(2) * bqy;
-        o5 = -(bqx + bqy) - R(3) * (brx + bry);
-        o6 = bqx - bqy + R(3) * (brx - bry);
-        o9 = R(2) * bqx + brx;
-        o10 = R(2) * bqy + bry;
+        o1 += bjx;
+        o2 += bjy;
+        o9 += R(2) * bjx;
+        o10 += R(2) * bjy;
+        odx += bjx;
+        ody += bjy;
     }
-    const R e1 = ec1 + aXX - R(4) * aXXe;
-    const R e2 = ec1 - aXX + R(4) * aXXe;
+    const R o5 = odx + ody, o6 = ody - odx;
+    const R t1 = aXX - R(4) * aXXe, t9 = R(4) * aXX + aXXe;
+    const R e1 = ec1 + t1;
+    const R e2 = ec1 - t1;
     const R e5 = ec5 + aXY;
     const R e6 = ec5 - aXY;
-    const R e9 = ec9 + R(4) * aXX + aXXe;
-    const R e10 = ec9 - R(4) * aXX - aXXe;
+    const R e9 = ec9 + t9;
+    const R e10 = ec9 - t9;
 
     g[0] -= e0;
     g[1] -= e1 + o1;
