@@ -123,6 +123,17 @@ def next_chunk(done, steps, diag_every):
     return k, (done + k) % diag_every == 0
 
 
+def graph_length(graph_k, steps, spl):
+    """Steps per captured graph: graph_k, or for shorter runs the largest
+    multiple of 2 spl that fits (an even number of whole launches); 0: none."""
+    if not graph_k:
+        return 0
+    if steps >= graph_k:
+        return graph_k
+    unit = 2 * spl
+    return steps // unit * unit if steps >= unit else 0
+
+
 def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0):
     """Time one form on the n x n wave.  cfg fixes the launch configuration;
     tune_steps > 0 lets the library's autotuner pick it on this device instead
@@ -144,8 +155,14 @@ def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0
         lat.autotune(tune_steps)
         lat.init_moments(*fields)
     launch = lat.launch_config()
-    if graph_k:
-        lat.use_graph(graph_k)
+    spl = launch["steps_per_launch"]
+    gk = graph_length(graph_k, steps, spl)
+    if gk:
+        # set-up, like the autotuning: capture the graph (an even number of
+        # launches, so one capture serves) and start again from the initial state
+        lat.use_graph(gk)
+        lat.step(gk)
+        lat.init_moments(*fields)
     lat.step(warmup)
     d0 = lat.diagnostics()
     torch.cuda.synchronize()
@@ -154,28 +171,34 @@ def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0
     done = 0
     while done < steps:
         k, diag_now = next_chunk(done, steps, diag_every)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        lat.step(k)
-        b.record(stream)
-        ev.append((a, b, k))
+        # whole launches of the chosen configuration, timed apart from a remainder
+        # of shorter launches, so the per-launch time is that of the chosen kernel
+        for part in (k // spl * spl, k % spl):
+            if part == 0:
+                continue
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lat.step(part)
+            b.record(stream)
+            ev.append((a, b, part, part % spl == 0))
         if diag_now:
             lat.diagnostics()  # FP64 reductions (synchronises)
         done += k
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
+    kern_ms = sum(a.elapsed_time(b) for a, b, _, _ in ev)
+    whole = [(a.elapsed_time(b), k) for a, b, k, w in ev if w]
+    per_launch = (sum(t for t, _ in whole) / (sum(k for _, k in whole) / spl)) if whole else kern_ms / steps * spl
     d1 = lat.diagnostics()
     nodes = n * n
     drift = abs(d1["sum_rho"] - d0["sum_rho"]) / d0["sum_rho"]
     lat.destroy()
     del lat
     torch.cuda.empty_cache()
-    spl = launch["steps_per_launch"]
-    return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=kern_ms / steps * spl,
+    return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=per_launch,
                 mlups=nodes * steps / wall / 1e6, kernel_mlups=nodes / (kern_ms / steps * 1e-3) / 1e6,
-                mass_drift=drift, nodes=nodes, spl=spl, launch=launch)
+                mass_drift=drift, nodes=nodes, spl=spl, launch=launch, graph_steps=gk)
 
 
 def cavity_specs(count=64, seed=4):
@@ -748,7 +771,7 @@ def main():
     ap.add_argument("--workload", default="wave4096",
                     choices=["wave4096", "cavities64", "channels128", "wave32", "cavity256"])
     ap.add_argument("--size", type=int, default=4096, help="side of the periodic wave (wave4096)")
-    ap.add_argument("--diag-every", type=int, default=1000)
+    ap.add_argument("--diag-every", type=int, default=960)
     ap.add_argument("--fp64-steps", type=int, default=-1, help="steps of the plain FP64 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -852,7 +875,7 @@ def main():
         "config": {"workload": "periodic %dx%d transverse shear + acoustic wave" % (n, n), "nx": n, "ny": n,
                    "form": "fp32-deviation", "launch": r32["launch"],
                    "launch_choice": "autotuned on this device" if tune32 else "fixed",
-                   "graph_steps": graph_k, "diag_every": args.diag_every},
+                   "graph_steps": r32["graph_steps"], "diag_every": args.diag_every},
         "roofline": roof32,
         "cpu_baseline": cpu,
         "fp64": {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),

@@ -50,12 +50,13 @@ def test_traffic_is_null_for_other_sources_or_launches(path, monkeypatch):
 
 @pytest.mark.parametrize("path", TABLES, ids=os.path.basename)
 def test_recorded_traffic_is_at_least_the_compulsory_bytes(path):
-    # a launch of s steps reads and writes every population at least once: 1/s of
-    # the algorithmic bytes of s single steps (less only through a counting error)
+    # a launch of any number of steps reads and writes every population at least
+    # once (less only through a counting error), the roofline's bytes per launch
     _, recs = _records(path)
     for key, rec in recs:
-        spl = rec["launch"]["steps_per_launch"]
-        assert rec["bytes_per_launch"] >= 0.98 * rec["algorithmic_bytes_per_launch"] / spl, (key, rec["launch"])
+        es = 8 if "double" in rec["kernels"][0]["kernel"] else 4
+        assert rec["compulsory_bytes_per_launch"] == 26 * es * rec["nodes"]
+        assert rec["bytes_per_launch"] >= 0.98 * rec["compulsory_bytes_per_launch"], (key, rec["launch"])
         assert abs(rec["bytes_per_launch"] - (rec["fetch_bytes"] + rec["write_bytes"])) <= 1.0
 
 
@@ -99,3 +100,12 @@ def test_roofline_fraction_is_a_fraction(precision, spl):
     cap = bench.SIMDS * bench.CLOCK_GHZ * 1e9 * 2 * ideal_ms * 1e-3 / 4
     assert slower["valu_issue"]["frac"] == pytest.approx(1.0e8 / cap, rel=1e-3)
     assert bench.ALU_PEAK_TFLOPS == pytest.approx(78.6, abs=0.1)
+
+
+@pytest.mark.parametrize("graph_k,steps,spl,expect", [(120, 2040, 3, 120), (120, 20, 3, 18), (120, 5, 3, 0),
+                                                      (120, 20, 1, 20), (0, 2040, 3, 0), (120, 11, 2, 8)])
+def test_graph_length_is_whole_even_launches(graph_k, steps, spl, expect):
+    gk = bench.graph_length(graph_k, steps, spl)
+    assert gk == expect
+    if gk:
+        assert gk % spl == 0 and (gk // spl) % 2 == 0 and gk <= steps
