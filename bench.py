@@ -212,7 +212,7 @@ def cavity_specs(count=64, seed=4):
         kw = workloads.cavity_parameter_set(c["Pr"])
         st, d = lbm13.derive(**kw)
         cf = workloads.cavity_forcing(c["nx"], c["Ra"], c["Pr"], d["nu"], d["kappa"],
-                                      dT_max=workloads.cavity_dT_cap(c["nx"]))
+                                      dT_max=workloads.cavity_dT_cap(c["nx"]), cs=d["cs2"] ** 0.5)
         E0 = kw["E0"]
         out.append(dict(nx=c["nx"], ny=c["ny"], kw=dict(kw, g=(0.0, -cf["g"])),
                         sides=((2, 2, 1, 1), (0, 0, 0, 0), (E0 + cf["dT"] / 2, E0 - cf["dT"] / 2, 0, 0)),

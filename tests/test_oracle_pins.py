@@ -581,13 +581,14 @@ def test_couette_wall_temperature_is_imposed():
 
 @pytest.mark.parametrize("Pr", [0.5, 0.71, 1.0, 1.5, 3.0, 7.0])
 def test_cavity_parameter_sets_are_linearly_stable(Pr):
-    """The per-Pr parameter sets used for the batched cavities keep every linear
-    mode bounded (max |lambda| <= 1) at rest and with |u| <= 0.05 and |E - E0| <= 0.3."""
+    """The parameter set of the batched cavities keeps every linear mode bounded
+    (max |lambda| <= 1) at each Prandtl number of the batch's range, at rest and
+    with |u| <= 0.07 and |E - E0| <= 0.3."""
     kw = workloads.cavity_parameter_set(Pr)
     p = oracle.params(**kw)
     assert oracle.derive(p)[0] == 0
-    for dE in (0.0, 0.3):
-        for U in ((0.0, 0.0), (0.05, 0.0), (0.035, 0.035)):
+    for dE in (0.0, 0.3, -0.3):
+        for U in ((0.0, 0.0), (0.05, 0.0), (0.035, 0.035), (0.0, 0.07)):
             w = 0.0
             for kx in np.linspace(0, np.pi, 11):
                 for ky in np.linspace(0, kx, 11):
