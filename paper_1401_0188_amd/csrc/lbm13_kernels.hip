@@ -377,12 +377,12 @@ __device__ __forceinline__ void fix_link(const Src& A, const Dom<R>& D, int w, i
     g[I] = (abb ? -src : src) + wall_term<I>(ws, abb);
 }
 
+template <typename R, typename Src, typename Side>
+__device__ __forceinline__ void wall_fixups(const Src& A, const Side& SD, const Dom<R>& D, int x, int y, R g[13]);
+
 // Gather for a node within two nodes of a wall: every link is first read with
 // in-bounds coordinates, then the links whose source lies beyond a wall are
-// replaced (bounce-back for links with a tangential component and for every
-// link at an adiabatic wall, anti-bounce-back for links normal to a temperature
-// wall; sec. 7).  y walls are applied first and x walls last, so a diagonal
-// source beyond two walls takes the West/East wall.
+// replaced (wall_fixups).
 template <typename R, typename Src, typename Side>
 __device__ __forceinline__ void gather_wall(const Src& A, const Side& SD, const Dom<R>& D, int x, int y, R g[13]) {
     const int xm1 = A.cx(x - 1), xm2 = A.cx(x - 2), xp1 = A.cx(x + 1), xp2 = A.cx(x + 2);
@@ -400,6 +400,17 @@ __device__ __forceinline__ void gather_wall(const Src& A, const Side& SD, const 
     g[10] = A.get(10, x, ym2);
     g[11] = A.get(11, xp2, y);
     g[12] = A.get(12, x, yp2);
+    wall_fixups(A, SD, D, x, y, g);
+}
+
+// The wall fix-ups of a gather: the links whose source lies beyond a wall
+// replaced (bounce-back for links with a tangential component and for every
+// link at an adiabatic wall, anti-bounce-back for links normal to a temperature
+// wall; sec. 7).  y walls are applied first and x walls last, so a diagonal
+// source beyond two walls takes the West/East wall.  Every other link is left
+// as gathered.
+template <typename R, typename Src, typename Side>
+__device__ __forceinline__ void wall_fixups(const Src& A, const Side& SD, const Dom<R>& D, int x, int y, R g[13]) {
     R r0, e0, r1;
     if (!D.yper && y < 2) {  // South wall: links with v_y > 0
         SD.get(D, 2, x, r0, e0, r1);
@@ -545,7 +556,8 @@ __global__ __launch_bounds__(256) void step_kernel(const R* __restrict__ src, R*
 // equals two single steps; HBM traffic per step is about halved (the halo is
 // re-read from L2 by neighbouring tiles), for (TW+4)(TH+4)/(TW TH) times the
 // phase-1 collision work.  Wall-layer densities of step t + 1 are kept in LDS
-// for phase 2's wall states.
+// for phase 2's wall states; phase 2 reads every node's sources with the plain
+// stencil and then replaces the links from beyond a wall (wall_fixups).
 // Waves per SIMD that a workgroup of nt threads with lds_bytes of LDS allows
 // (160 KB of LDS and at most 8 waves per SIMD on a CU of 4 SIMDs); the
 // multi-step kernels ask the compiler for the registers of that occupancy.
@@ -705,12 +717,9 @@ void step2_kernel(const R* __restrict__ src, R* __restrict__ dst,
         if (X >= D.nx || Y >= D.ny) continue;
         R g[13];
         const bool near = (!D.xper && (X < 2 || X >= D.nx - 2)) || (!D.yper && (Y < 2 || Y >= D.ny - 2));
-        if (tile_walls) {
-            gather_wall(L, LS, D, X, Y, g);
-        } else {
 #pragma unroll
-            for (int i = 0; i < 13; ++i) g[i] = lds[(i * RH + ly - kVY[i]) * RW + lx - kVX[i]];
-        }
+        for (int i = 0; i < 13; ++i) g[i] = lds[(i * RH + ly - kVY[i]) * RW + lx - kVX[i]];
+        if (tile_walls) wall_fixups(L, LS, D, X, Y, g);
         if (D.collide) collide(g, D);
         store_node(o, D.plane, Y * D.pitch + X, g);
         if (near) record_wall_layers(side, D, 1 - from, X, Y, g);
@@ -943,8 +952,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 // barrier, stores it and its layer values over the first level; phase 3
 // advances the tile, writes HBM and the side array of step t + 3.  Region
 // nodes beyond a wall (or past a ragged edge) gather from a clamped node and
-// store nothing; no gather of an in-domain node reads them.  Each node's
-// arithmetic is the single-step kernel's.
+// store nothing.  Phases 2 and 3 read every node's sources with the plain
+// stencil, then replace the links from beyond a wall (wall_fixups): those
+// reads land in slots beyond the wall, never written, and are discarded.
+// Each node's arithmetic is the single-step kernel's.
 template <typename R, int TW, int TH, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu(
     (13 * (TW + 8) * (TH + 8) + 6 * (TW + TH + 16)) * (int)sizeof(R), NT)))) void step3_wall_kernel(
@@ -1002,6 +1013,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
 
     // Phase 2: t + 1 -> t + 2 over the second level, gathers from the first
     // (coordinates unwrapped on periodic axes, as the region stores them).
+    // The plain stencil's reads are those of gather_wall for every link it
+    // keeps, so the result is the same.
     const LdsSrc<R, W1, H1> L1{lds, o1x, o1y, D.nx, D.ny, D.xper, D.yper};
     const LdsSide<R, W1, H1> S1{xs, ys, o1x, o1y};
     const bool walls2 =
@@ -1014,12 +1027,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
         const int lx = r % W2, ly = r / W2, X = o2x + lx, Y = o2y + ly;
         v2[k] = r < N2 && (D.xper || (X >= 0 && X < D.nx)) && (D.yper || (Y >= 0 && Y < D.ny));
         if (!v2[k]) continue;
-        if (walls2) {
-            gather_wall(L1, S1, D, X, Y, h[k]);
-        } else {
 #pragma unroll
-            for (int i = 0; i < 13; ++i) h[k][i] = lds[(i * H1 + ly + 2 - kVY[i]) * W1 + lx + 2 - kVX[i]];
-        }
+        for (int i = 0; i < 13; ++i) h[k][i] = lds[(i * H1 + ly + 2 - kVY[i]) * W1 + lx + 2 - kVX[i]];
+        if (walls2) wall_fixups(L1, S1, D, X, Y, h[k]);
         if (D.collide) collide(h[k], D);
     }
     __syncthreads();
@@ -1043,12 +1053,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
         const int X = o2x + lx, Y = o2y + ly;
         if (X >= D.nx || Y >= D.ny) continue;
         R q[13];
-        if (walls3) {
-            gather_wall(L2, S2, D, X, Y, q);
-        } else {
 #pragma unroll
-            for (int i = 0; i < 13; ++i) q[i] = lds[(i * H2 + ly - kVY[i]) * W2 + lx - kVX[i]];
-        }
+        for (int i = 0; i < 13; ++i) q[i] = lds[(i * H2 + ly - kVY[i]) * W2 + lx - kVX[i]];
+        if (walls3) wall_fixups(L2, S2, D, X, Y, q);
         if (D.collide) collide(q, D);
         store_node(o, D.plane, Y * D.pitch + X, q);
         record_wall_layers(side, D, 1 - from, X, Y, q);
