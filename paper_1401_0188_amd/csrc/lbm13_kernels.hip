@@ -942,6 +942,33 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 }
 
 // ---------------------------------------------------------------------------
+// The nodes a level of the general multi-step kernel computes: the slots of
+// its region inside the domain (on a walled axis) and within reach of the
+// tile's nodes (a ragged tile needs fewer columns or rows), numbered row by row
+// over that window, so that waves past its end skip the level.  Slot r of the
+// window is region slot (x0 + r mod w, y0 + r div w); the quotient is taken in
+// FP32 as (r + 1/2) / w, exact for r < 4096 and w <= 80 (the distance of
+// (r + 1/2) / w from an integer, 1 / (2w), exceeds the rounding error).
+struct LevelWindow {
+    int x0, y0, w, n;
+    float inv;
+    __device__ __forceinline__ void slot(int r, int& lx, int& ly) const {
+        const int q = (int)(((float)r + 0.5f) * inv);
+        ly = y0 + q;
+        lx = x0 + r - q * w;
+    }
+};
+
+// Window of a level whose region starts at (ox, oy) and whose tile's nodes
+// reach ex columns and ey rows of it.
+template <typename R>
+__device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int oy, int ex, int ey) {
+    const int xa = D.xper ? 0 : max(0, -ox), xb = D.xper ? ex : min(ex, D.nx - ox);
+    const int ya = D.yper ? 0 : max(0, -oy), yb = D.yper ? ey : min(ey, D.ny - oy);
+    return LevelWindow{xa, ya, xb - xa, (xb - xa) * (yb - ya), 1.0f / (float)(xb - xa)};
+}
+
+// ---------------------------------------------------------------------------
 // Three steps per launch on the other tiles: tiles that reach a wall (their
 // region, a tile plus four nodes on each side, or its gathers), a ragged
 // domain edge or a periodic axis shorter than the region.  The state of each
@@ -981,29 +1008,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
     const GlobalSide<R> GS{side, from};
     const bool walls1 =
         (!D.xper && (o1x < 2 || o1x + W1 > D.nx - 2)) || (!D.yper && (o1y < 2 || o1y + H1 > D.ny - 2));
+    const int tw3 = min(TW, D.nx - tl.x0), th3 = min(TH, D.ny - tl.y0);  // the tile's nodes
+    const LevelWindow w1 = level_window(D, o1x, o1y, tw3 + 8, th3 + 8);
     R g[NI1][13];
-    int X1[NI1], Y1[NI1];
+    int X1[NI1], Y1[NI1], l1x[NI1], l1y[NI1];
     bool v1[NI1];
 #pragma unroll
     for (int k = 0; k < NI1; ++k) {
-        const int r = min(tid + k * NT, N1 - 1);
-        int X = o1x + r % W1, Y = o1y + r / W1;
-        bool v = tid + k * NT < N1;
+        w1.slot(min(tid + k * NT, w1.n - 1), l1x[k], l1y[k]);
+        int X = o1x + l1x[k], Y = o1y + l1y[k];
         // a region wraps at most once around an axis at least as long as itself
         if (D.xper) X = D.nx >= W1 ? wrap(X, D.nx) : pmod(X, D.nx);
-        else { v = v && X >= 0 && X < D.nx; X = min(max(X, 0), D.nx - 1); }
         if (D.yper) Y = D.ny >= H1 ? wrap(Y, D.ny) : pmod(Y, D.ny);
-        else { v = v && Y >= 0 && Y < D.ny; Y = min(max(Y, 0), D.ny - 1); }
         X1[k] = X;
         Y1[k] = Y;
-        v1[k] = v;
+        v1[k] = tid + k * NT < w1.n;
+        if (!v1[k]) continue;
         if (walls1) gather_wall(G, GS, D, X, Y, g[k]);
         else gather_bulk(a, D, X, Y, g[k]);
     }
 #pragma unroll
     for (int k = 0; k < NI1; ++k) {
         if (!v1[k]) continue;
-        const int r = tid + k * NT, lx = r % W1, ly = r / W1;
+        const int lx = l1x[k], ly = l1y[k];
         if (D.collide) collide(g[k], D);
 #pragma unroll
         for (int i = 0; i < 13; ++i) lds[(i * H1 + ly) * W1 + lx] = g[k][i];
@@ -1019,13 +1046,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
     const LdsSide<R, W1, H1> S1{xs, ys, o1x, o1y};
     const bool walls2 =
         (!D.xper && (o2x < 2 || o2x + W2 > D.nx - 2)) || (!D.yper && (o2y < 2 || o2y + H2 > D.ny - 2));
+    const LevelWindow w2 = level_window(D, o2x, o2y, tw3 + 4, th3 + 4);
     R h[NI2][13];
+    int l2x[NI2], l2y[NI2];
     bool v2[NI2];
 #pragma unroll
     for (int k = 0; k < NI2; ++k) {
-        const int r = tid + k * NT;
-        const int lx = r % W2, ly = r / W2, X = o2x + lx, Y = o2y + ly;
-        v2[k] = r < N2 && (D.xper || (X >= 0 && X < D.nx)) && (D.yper || (Y >= 0 && Y < D.ny));
+        w2.slot(min(tid + k * NT, w2.n - 1), l2x[k], l2y[k]);
+        const int lx = l2x[k], ly = l2y[k], X = o2x + lx, Y = o2y + ly;
+        v2[k] = tid + k * NT < w2.n;
         if (!v2[k]) continue;
 #pragma unroll
         for (int i = 0; i < 13; ++i) h[k][i] = lds[(i * H1 + ly + 2 - kVY[i]) * W1 + lx + 2 - kVX[i]];
@@ -1036,7 +1065,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
 #pragma unroll
     for (int k = 0; k < NI2; ++k) {
         if (!v2[k]) continue;
-        const int r = tid + k * NT, lx = r % W2, ly = r / W2;
+        const int lx = l2x[k], ly = l2y[k];
 #pragma unroll
         for (int i = 0; i < 13; ++i) lds[(i * H2 + ly) * W2 + lx] = h[k][i];
         record_region_layers<R, W2, H2>(xs, ys, D, o2x + lx, o2y + ly, lx, ly, h[k]);
@@ -1048,10 +1077,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
     const LdsSide<R, W2, H2> S2{xs, ys, o2x, o2y};
     const bool walls3 = (!D.xper && (tl.x0 < 2 || tl.x0 + TW > D.nx - 2)) ||
                         (!D.yper && (tl.y0 < 2 || tl.y0 + TH > D.ny - 2));
-    for (int r = tid; r < N3; r += NT) {
-        const int lx = r % TW + 2, ly = r / TW + 2;
+    const LevelWindow w3{2, 2, tw3, tw3 * th3, 1.0f / (float)tw3};
+    for (int r = tid; r < w3.n; r += NT) {
+        int lx, ly;
+        w3.slot(r, lx, ly);
         const int X = o2x + lx, Y = o2y + ly;
-        if (X >= D.nx || Y >= D.ny) continue;
         R q[13];
 #pragma unroll
         for (int i = 0; i < 13; ++i) q[i] = lds[(i * H2 + ly - kVY[i]) * W2 + lx - kVX[i]];
