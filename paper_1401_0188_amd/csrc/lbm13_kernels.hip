@@ -950,12 +950,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 // FP32 as (r + 1/2) / w, exact for r < 4096 and w <= 80 (the distance of
 // (r + 1/2) / w from an integer, 1 / (2w), exceeds the rounding error).
 struct LevelWindow {
-    int x0, y0, w, n;
-    float inv;
+    int x0, y0, w, h, n;
+    bool col;   // numbered column by column instead: a wave then takes 64 / h
+                // columns, so the nodes next to an x wall fall into one or two
+                // waves and only those run the wall fix-ups
+    float inv;  // 1 / w, or 1 / h by columns
     __device__ __forceinline__ void slot(int r, int& lx, int& ly) const {
-        const int q = (int)(((float)r + 0.5f) * inv);
-        ly = y0 + q;
-        lx = x0 + r - q * w;
+        const int q = (int)(((float)r + 0.5f) * inv), m = r - q * (col ? h : w);
+        lx = x0 + (col ? q : m);
+        ly = y0 + (col ? m : q);
     }
 };
 
@@ -965,7 +968,7 @@ template <typename R>
 __device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int oy, int ex, int ey) {
     const int xa = D.xper ? 0 : max(0, -ox), xb = D.xper ? ex : min(ex, D.nx - ox);
     const int ya = D.yper ? 0 : max(0, -oy), yb = D.yper ? ey : min(ey, D.ny - oy);
-    return LevelWindow{xa, ya, xb - xa, (xb - xa) * (yb - ya), 1.0f / (float)(xb - xa)};
+    return LevelWindow{xa, ya, xb - xa, yb - ya, (xb - xa) * (yb - ya), false, 1.0f / (float)(xb - xa)};
 }
 
 // ---------------------------------------------------------------------------
@@ -985,13 +988,14 @@ __device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int
 // Each node's arithmetic is the single-step kernel's.
 template <typename R, int TW, int TH, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu(
-    (13 * (TW + 8) * (TH + 8) + 6 * (TW + TH + 16)) * (int)sizeof(R), NT)))) void step3_wall_kernel(
+    (13 * (TW + 9) * (TH + 8) + 6 * (TW + TH + 16)) * (int)sizeof(R), NT)))) void step3_wall_kernel(
     const R* __restrict__ src, R* __restrict__ dst, const Dom<R>* __restrict__ doms, const Tile* __restrict__ tiles,
     int ntiles, R* __restrict__ side, int from) {
     constexpr int W1 = TW + 8, H1 = TH + 8, W2 = TW + 4, H2 = TH + 4;
-    constexpr int N1 = W1 * H1, N2 = W2 * H2, N3 = TW * TH;
+    constexpr int N1 = W1 * H1, N2 = W2 * H2;
+    constexpr int P1 = W1 + 1, P2 = W2 + 1;  // odd LDS row pitches: a column is conflict-free
     constexpr int NI1 = (N1 + NT - 1) / NT, NI2 = (N2 + NT - 1) / NT;
-    __shared__ R lds[13 * N1];
+    __shared__ R lds[13 * H1 * P1];
     __shared__ R xs[2 * H1 * 3];
     __shared__ R ys[2 * W1 * 3];
     const int t = xcd_tile(blockIdx.x, ntiles);
@@ -1033,7 +1037,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
         const int lx = l1x[k], ly = l1y[k];
         if (D.collide) collide(g[k], D);
 #pragma unroll
-        for (int i = 0; i < 13; ++i) lds[(i * H1 + ly) * W1 + lx] = g[k][i];
+        for (int i = 0; i < 13; ++i) lds[(i * H1 + ly) * P1 + lx] = g[k][i];
         record_region_layers<R, W1, H1>(xs, ys, D, X1[k], Y1[k], lx, ly, g[k]);
     }
     __syncthreads();
@@ -1042,11 +1046,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
     // (coordinates unwrapped on periodic axes, as the region stores them).
     // The plain stencil's reads are those of gather_wall for every link it
     // keeps, so the result is the same.
-    const LdsSrc<R, W1, H1> L1{lds, o1x, o1y, D.nx, D.ny, D.xper, D.yper};
+    const LdsSrc<R, P1, H1> L1{lds, o1x, o1y, D.nx, D.ny, D.xper, D.yper};
     const LdsSide<R, W1, H1> S1{xs, ys, o1x, o1y};
     const bool walls2 =
         (!D.xper && (o2x < 2 || o2x + W2 > D.nx - 2)) || (!D.yper && (o2y < 2 || o2y + H2 > D.ny - 2));
-    const LevelWindow w2 = level_window(D, o2x, o2y, tw3 + 4, th3 + 4);
+    const bool xwall2 = !D.xper && (o2x < 2 || o2x + W2 > D.nx - 2);
+    const LevelWindow r2 = level_window(D, o2x, o2y, tw3 + 4, th3 + 4);
+    const LevelWindow w2{r2.x0, r2.y0, r2.w, r2.h, r2.n, xwall2, xwall2 ? 1.0f / (float)r2.h : r2.inv};
     R h[NI2][13];
     int l2x[NI2], l2y[NI2];
     bool v2[NI2];
@@ -1057,7 +1063,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
         v2[k] = tid + k * NT < w2.n;
         if (!v2[k]) continue;
 #pragma unroll
-        for (int i = 0; i < 13; ++i) h[k][i] = lds[(i * H1 + ly + 2 - kVY[i]) * W1 + lx + 2 - kVX[i]];
+        for (int i = 0; i < 13; ++i) h[k][i] = lds[(i * H1 + ly + 2 - kVY[i]) * P1 + lx + 2 - kVX[i]];
         if (walls2) wall_fixups(L1, S1, D, X, Y, h[k]);
         if (D.collide) collide(h[k], D);
     }
@@ -1067,24 +1073,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
         if (!v2[k]) continue;
         const int lx = l2x[k], ly = l2y[k];
 #pragma unroll
-        for (int i = 0; i < 13; ++i) lds[(i * H2 + ly) * W2 + lx] = h[k][i];
+        for (int i = 0; i < 13; ++i) lds[(i * H2 + ly) * P2 + lx] = h[k][i];
         record_region_layers<R, W2, H2>(xs, ys, D, o2x + lx, o2y + ly, lx, ly, h[k]);
     }
     __syncthreads();
 
     // Phase 3: t + 2 -> t + 3 over the tile, gathers from the second level.
-    const LdsSrc<R, W2, H2> L2{lds, o2x, o2y, D.nx, D.ny, D.xper, D.yper};
+    const LdsSrc<R, P2, H2> L2{lds, o2x, o2y, D.nx, D.ny, D.xper, D.yper};
     const LdsSide<R, W2, H2> S2{xs, ys, o2x, o2y};
     const bool walls3 = (!D.xper && (tl.x0 < 2 || tl.x0 + TW > D.nx - 2)) ||
                         (!D.yper && (tl.y0 < 2 || tl.y0 + TH > D.ny - 2));
-    const LevelWindow w3{2, 2, tw3, tw3 * th3, 1.0f / (float)tw3};
+    const LevelWindow w3{2, 2, tw3, th3, tw3 * th3, false, 1.0f / (float)tw3};
     for (int r = tid; r < w3.n; r += NT) {
         int lx, ly;
         w3.slot(r, lx, ly);
         const int X = o2x + lx, Y = o2y + ly;
         R q[13];
 #pragma unroll
-        for (int i = 0; i < 13; ++i) q[i] = lds[(i * H2 + ly - kVY[i]) * W2 + lx - kVX[i]];
+        for (int i = 0; i < 13; ++i) q[i] = lds[(i * H2 + ly - kVY[i]) * P2 + lx - kVX[i]];
         if (walls3) wall_fixups(L2, S2, D, X, Y, q);
         if (D.collide) collide(q, D);
         store_node(o, D.plane, Y * D.pitch + X, q);
