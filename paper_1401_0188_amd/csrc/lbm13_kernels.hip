@@ -980,11 +980,13 @@ __device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int
 // array of step t), phase 2 the (TW + 4) x (TH + 4) region from LDS into
 // registers (wall fix-ups from the layer values phase 1 kept), then, after a
 // barrier, stores it and its layer values over the first level; phase 3
-// advances the tile, writes HBM and the side array of step t + 3.  Region
-// nodes beyond a wall (or past a ragged edge) gather from a clamped node and
-// store nothing.  Phases 2 and 3 read every node's sources with the plain
-// stencil, then replace the links from beyond a wall (wall_fixups): those
-// reads land in slots beyond the wall, never written, and are discarded.
+// advances the tile, writes HBM and the side array of step t + 3.  Each level
+// computes only the window of its region inside the domain and within reach
+// of the tile's nodes (LevelWindow); region slots beyond a wall are never
+// written.  Phases 2 and 3 read every node's sources with the plain stencil,
+// then replace the links from beyond a wall (wall_fixups): those reads land in
+// the unwritten slots and are discarded.  In tiles at an x wall phase 2 is
+// numbered by columns, so that the nodes next to the wall share few waves.
 // Each node's arithmetic is the single-step kernel's.
 template <typename R, int TW, int TH, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu(
@@ -994,6 +996,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
     constexpr int W1 = TW + 8, H1 = TH + 8, W2 = TW + 4, H2 = TH + 4;
     constexpr int N1 = W1 * H1, N2 = W2 * H2;
     constexpr int P1 = W1 + 1, P2 = W2 + 1;  // odd LDS row pitches: a column is conflict-free
+    static_assert(W1 <= 80 && H1 <= 80 && ((N1 + NT - 1) / NT) * NT <= 4096, "LevelWindow's quotient range");
     constexpr int NI1 = (N1 + NT - 1) / NT, NI2 = (N2 + NT - 1) / NT;
     __shared__ R lds[13 * H1 * P1];
     __shared__ R xs[2 * H1 * 3];
@@ -1007,7 +1010,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
     const int tid = threadIdx.x;
 
     // Phase 1: t -> t + 1 over the first level, gathers of all a thread's nodes
-    // issued before the first collision.
+    // issued before the first collision.  The window lies inside the domain on
+    // a walled axis, so no coordinate needs a clamp.
     const GlobalSrc<R> G{a, D.plane, D.pitch, D.nx, D.ny, D.xper, D.yper};
     const GlobalSide<R> GS{side, from};
     const bool walls1 =
