@@ -1542,6 +1542,41 @@ def test_every_three_step_tile_shape(precision):
             lat.destroy()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_general_three_step_kernel_level_windows(precision):
+    """The general three-step kernel computes, at each level, only the window
+    of its region inside the domain and within reach of the tile's nodes, and
+    numbers the second level by columns in tiles at an x wall.  Domains one
+    column and one row past whole tiles (ragged remainders of width 1 and of
+    height TH - 1), walls on x only, on every side, and walls on y with a
+    periodic x axis shorter than a region, every tile on the general kernel and
+    with the interior tiles split off, against the oracle after nine steps."""
+    lbm13 = _lb()
+    for tw, th in lbm13.STEP3_TILE_SHAPES[precision][:3]:
+        for nx, ny, kinds, u_t, T_w in ((tw + 1, 2 * th - 1, (2, 2, 0, 0), (0, 0, 0, 0), (-1.99, -2.01, 0, 0)),
+                                        (2 * tw + 1, th + 3, (2, 2, 1, 1), (0, 0, 0.02, 0), (-1.99, -2.01, 0, 0)),
+                                        (tw // 2 + 3, 2 * th + 1, (0, 0, 2, 1), (0, 0, 0, -0.01), (0, 0, -1.98, 0))):
+            fields = workloads.cavity_fields(nx, ny=ny, seed=nx + ny, dT=0.01)
+            for interior in (False, True):
+                say("general three-step kernel windows: tile %dx%d, %d x %d, sides %s, interior kernel %s, precision %d"
+                    % (tw, th, nx, ny, kinds, interior, precision))
+                po, pl = params_pair(g=(0.0, -1e-4), F0=(1e-5, 0.0))
+                lat = lbm13.Lattice(nx, ny, precision)
+                lat.set_fused_tile(tw, th)
+                lat.set_steps_per_launch(3)
+                lat.set_interior_kernel(interior)
+                lat.set_params(sides=lbm13.make_sides(kinds, u_t, T_w), **pl)
+                lat.init_moments(*fields)
+                lat.step(9)
+                f = oracle.run(oracle.init(*fields, po), po, oracle.sides(kinds, u_t, T_w), 9)
+                gm = [t.cpu().numpy() for t in lat.moments()]
+                if precision == 0:
+                    assert_fp64(lat.get_state().cpu().numpy(), gm, oracle.collide(f, po), oracle.moments(f, po))
+                else:
+                    assert_fp32(gm, oracle.moments(f, po))
+                lat.destroy()
+
+
 def test_three_steps_per_launch_streaming_is_bit_exact():
     """Collisions off, walls at rest and adiabatic (every wall term is zero, so
     no arithmetic is left): three-step launches are exactly the oracle's
