@@ -312,8 +312,8 @@ __device__ __forceinline__ R wall_term(const WallState<R>& ws, bool abb) {
 // wrapped on a periodic axis, clamped on a walled axis (a clamped link is
 // always replaced by a wall fix-up).
 //   GlobalSrc: the stored state in HBM (domain coordinates).
-//   LdsSrc: a tile's region (tile plus two nodes on each side) in LDS, indexed
-//   by unwrapped domain coordinates relative to the region's origin.
+//   LdsSrc: a tile's region in LDS, RH rows of pitch RW per population,
+//   indexed by unwrapped domain coordinates relative to the region's origin.
 template <typename R>
 struct GlobalSrc {
     const R* __restrict__ b;
