@@ -77,9 +77,9 @@ def launch_kernels(launch):
     spl = launch["steps_per_launch"]
     if spl == 1:
         return (1, tuple(launch["tile"]))
-    if spl == 2:
+    if spl == 2:  # two steps take mode 2 as 1
         return (2, tuple(launch["fused_tile"]), bool(launch["interior_kernel"]))
-    return (3, tuple(launch["fused_tile"]), bool(launch["interior_kernel"]))
+    return (3, tuple(launch["fused_tile"]), int(launch["interior_kernel"]))
 
 
 def measured_record(key, launch, path=None):
@@ -816,7 +816,7 @@ def main():
     log("fp32-deviation %dx%d: %d warmup + %d steps" % (n, n, args.warmup, args.steps))
     def fixed(launch):
         return dict(spl=launch["steps_per_launch"], tile=tuple(launch["tile"]), fused_tile=tuple(launch["fused_tile"]),
-                    interior_kernel=bool(launch["interior_kernel"]))
+                    interior_kernel=int(launch["interior_kernel"]))
     cfg32, cfg64 = dict(BENCH_CONFIG[1]), dict(BENCH_CONFIG[0])
     tune32 = tune64 = args.tune_steps
     if args.launch_fp32:

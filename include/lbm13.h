@@ -262,9 +262,12 @@ int lbm13_set_fused_tile(lbm13_ctx *ctx, int tile_x, int tile_y);
  * kernel that keeps only the windows the next level reads in LDS,
  * concurrently with the general kernel on the other tiles; 0 runs every tile
  * on the general kernel (fewer, better balanced workgroups for batches of
- * small domains).  Two steps: identical results; three steps: identical with
- * collisions off, equal to rounding with them on (the two kernels contract
- * the same arithmetic differently).  EINVAL otherwise. */
+ * small domains); 2 runs, for three steps, both kinds of tile in one launch,
+ * in the tile table's spatial order, each on its path (neighbouring tiles
+ * then share their halo reads; two steps take 2 as 1).  Two steps: identical
+ * results; three steps: identical with collisions off, equal to rounding with
+ * them on (the kernels contract the same arithmetic differently).  EINVAL
+ * otherwise. */
 int lbm13_set_interior_kernel(lbm13_ctx *ctx, int on);
 
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -38,7 +38,8 @@ template <typename R>
 hipError_t launch_fourier(int, int, const R*, const Dom<R>*, int, int, const Tile*, int, int, double*, double*,
                           hipStream_t);
 template <typename R>
-hipError_t launch_step3(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int, bool, hipStream_t);
+hipError_t launch_step3(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int, bool, hipStream_t,
+                        bool);
 template <typename R>
 hipError_t launch_init(int, int, R*, const Dom<R>*, int, const double*, const double*, const double*, const double*,
                        const double*, hipStream_t);
@@ -228,7 +229,7 @@ struct lbm13_batch {
     int nfint = 0, nfedge = 0;            // interior / edge tiles of the fused table
     int n3int = 0, n3edge = 0;            // interior / edge tiles of the three-step table
     bool sourced = true;                  // some domain has a body force or an energy source
-    int split = 1;                        // 1: interior tiles run the compact-LDS kernel
+    int split = 1;                        // 1: interior tiles run the compact-LDS kernel beside; 2: in one launch (three steps)
     int tile_x = 64, tile_y = 8;
     int cur = 0;                          // buffer holding the current state
     char* bufp[2] = {nullptr, nullptr};   // the two population buffers
@@ -393,15 +394,24 @@ int rebuild(lbm13_batch* b) {
                     const bool xin = x0 >= 6 && x0 + tw + 6 <= nx, yin = y0 >= 6 && y0 + th + 6 <= ny;
                     const bool xok = x0 + tw <= nx && (k[0] == LBM13_PERIODIC ? nx >= tw + 12 : xin);
                     const bool yok = y0 + th <= ny && (k[2] == LBM13_PERIODIC ? ny >= th + 12 : yin);
-                    if (b->split && small && xok && yok)
-                        b->fused3.push_back(Tile{d, x0, y0, xin && yin ? 2 : 2 | 4});
+                    const bool interior = b->split && small && xok && yok;
+                    const Tile tl{d, x0, y0, interior ? (xin && yin ? 2 : 2 | 4) : 0};
+                    if (interior || b->split == 2)  // with one launch the table keeps the spatial order
+                        b->fused3.push_back(tl);
                     else
-                        f3edge.push_back(Tile{d, x0, y0, 0});
+                        f3edge.push_back(tl);
                 }
     }
-    b->n3int = (int)b->fused3.size();
-    b->n3edge = (int)f3edge.size();
-    b->fused3.insert(b->fused3.end(), f3edge.begin(), f3edge.end());
+    if (b->split == 2) {  // every tile in fused3, in order; n3int counts the interior ones
+        int nin = 0;
+        for (const Tile& tl : b->fused3) nin += (tl.flags & 2) ? 1 : 0;
+        b->n3int = nin;
+        b->n3edge = (int)b->fused3.size() - nin;
+    } else {
+        b->n3int = (int)b->fused3.size();
+        b->n3edge = (int)f3edge.size();
+        b->fused3.insert(b->fused3.end(), f3edge.begin(), f3edge.end());
+    }
     if ((int)b->fused3.size() > b->L.tfmax) return fail(b, LBM13_EINVAL, "three-step tile table overflow");
     b->lines.clear();
     for (int d = 0; d < b->count; ++d) {
@@ -578,18 +588,24 @@ hipError_t launch_three_steps(lbm13_batch* b, int from, hipStream_t s) {
     R* side = reinterpret_cast<R*>(b->ws + b->L.wall);
     const R* src = buf<R>(b, from);
     R* dst = buf<R>(b, 1 - from);
+    if (b->split == 2 && b->n3int > 0 && b->n3edge > 0)  // both kinds of tile, in order, in one launch
+        return lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->n3int, b->n3edge, side,
+                                      from, b->sourced, s, true);
+    if (b->split == 2)  // one kind only: its own kernel (the table holds just those tiles)
+        return lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->n3int, b->n3edge, side,
+                                      from, b->sourced, s, false);
     if (b->n3int == 0 || b->n3edge == 0 || !b->aux)
         return lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->n3int, b->n3edge, side,
-                                      from, b->sourced, s);
+                                      from, b->sourced, s, false);
     hipError_t e = hipEventRecord(b->ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->aux, b->ev_fork, 0);
     if (e == hipSuccess)
         e = lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles + b->n3int, 0, b->n3edge, side,
-                                   from, b->sourced, b->aux);
+                                   from, b->sourced, b->aux, false);
     if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->aux);
     if (e == hipSuccess)
         e = lbm13::launch_step3<R>(b->ftw, b->fth, src, dst, doms_dev<R>(b), tiles, b->n3int, 0, side, from,
-                                   b->sourced, s);
+                                   b->sourced, s, false);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join, 0);
     return e;
 }
@@ -714,7 +730,7 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
             for (int sp = 1; sp >= 0; --sp) cands.push_back(Cand{2, f[0], f[1], sp});
     for (auto& f : kStep3Shapes[b->precision == LBM13_FP64 ? 0 : 1])
         if (f[0] > 0)
-            for (int sp = 1; sp >= 0; --sp) cands.push_back(Cand{3, f[0], f[1], sp});
+            for (int sp = 2; sp >= 0; --sp) cands.push_back(Cand{3, f[0], f[1], sp});
     float best = 1e30f;
     Cand pick{b->spl, b->spl >= 2 ? b->ftw : b->tile_x, b->spl >= 2 ? b->fth : b->tile_y, b->split};
     int st = LBM13_OK;
@@ -730,6 +746,7 @@ int autotune_impl(lbm13_batch* b, int steps, int* tx, int* ty) {
         }
         if ((st = rebuild(b))) break;
         if (c.spl == 3 && !b->step3_ok) continue;  // not a three-step shape
+        if (c.spl == 3 && c.split == 2 && (b->n3int == 0 || b->n3edge == 0)) continue;  // the same launch as 1
         if ((st = step_impl<R>(b, 6))) break;
         (void)hipEventRecord(e0, b->stream);
         if ((st = step_impl<R>(b, steps))) break;
@@ -1109,7 +1126,7 @@ int lbm13_batch_autotune_cached(lbm13_batch* b, int steps, const char* cache_pat
     int cfg[6];
     if (lbm13::tune_cache_lookup(cache_path, key, cfg)) {
         // accept only a configuration this build supports for this precision
-        bool ok = cfg[0] >= 1 && cfg[0] <= 3 && valid_shape(cfg[1], cfg[2]) && (cfg[5] == 0 || cfg[5] == 1);
+        bool ok = cfg[0] >= 1 && cfg[0] <= 3 && valid_shape(cfg[1], cfg[2]) && cfg[5] >= 0 && cfg[5] <= 2;
         bool fused = false;
         for (auto& f : kFusedShapes) fused = fused || (f[0] == cfg[3] && f[1] == cfg[4]);
         ok = ok && fused && fused_fits(b->precision, cfg[3], cfg[4]);
@@ -1163,7 +1180,7 @@ int lbm13_batch_set_steps_per_launch(lbm13_batch* b, int k) {
 
 int lbm13_batch_set_interior_kernel(lbm13_batch* b, int on) {
     if (!b) return LBM13_EINVAL;
-    if (on != 0 && on != 1) return fail(b, LBM13_EINVAL, "interior kernel switch must be 0 or 1");
+    if (on < 0 || on > 2) return fail(b, LBM13_EINVAL, "interior kernel switch must be 0, 1 or 2");
     b->split = on;
     return rebuild(b);
 }

@@ -835,18 +835,16 @@ void step2_interior_kernel(const R* __restrict__ src, R* __restrict__ dst,
 // registers of the occupancy the LDS allows (FP32 64x16: two 1024-thread
 // workgroups, eight waves per SIMD; FP64 32x16: two 512-thread workgroups).
 // Sourced = false: no domain of the launch has a body force or energy source.
+template <int TW, int TH>
+constexpr int step3_window_lds() { return 2 + 13 * (TW + 4) * (TH + 4); }  // values
+
 template <typename R, int TW, int TH, int NT, bool Sourced>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
-    lds_waves_per_eu((2 + 13 * (TW + 4) * (TH + 4)) * (int)sizeof(R), NT)))) void step3_kernel(const R* __restrict__ src, R* __restrict__ dst,
-                                                   const Dom<R>* __restrict__ doms,
-                                                   const Tile* __restrict__ tiles, int ntiles) {
+__device__ __forceinline__ void step3_window_tile(R* lds, const Tile& tl, const R* __restrict__ src,
+                                                  R* __restrict__ dst, const Dom<R>* __restrict__ doms) {
     constexpr int W1 = TW + 8, H1 = TH + 8, W2 = TW + 4, H2 = TH + 4;
     constexpr int N1 = W1 * H1, N2 = W2 * H2, N3 = TW * TH;
     constexpr int NI1 = (N1 + NT - 1) / NT, NI2 = (N2 + NT - 1) / NT;
     constexpr int kLead = 2;  // keeps the window index of the population in slot 0 non-negative
-    __shared__ R lds[kLead + 13 * N2];
-    const int t = xcd_tile(blockIdx.x, ntiles);
-    const Tile tl = tiles[t];
     const Dom<R>& D = doms[tl.dom];
     const R* __restrict__ a = src + D.off;
     R* __restrict__ o = dst + D.off;
@@ -941,6 +939,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
     }
 }
 
+template <typename R, int TW, int TH, int NT, bool Sourced>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    lds_waves_per_eu(step3_window_lds<TW, TH>() * (int)sizeof(R), NT)))) void step3_kernel(
+    const R* __restrict__ src, R* __restrict__ dst, const Dom<R>* __restrict__ doms, const Tile* __restrict__ tiles,
+    int ntiles) {
+    __shared__ R lds[step3_window_lds<TW, TH>()];
+    const Tile tl = tiles[xcd_tile(blockIdx.x, ntiles)];
+    step3_window_tile<R, TW, TH, NT, Sourced>(lds, tl, src, dst, doms);
+}
+
+
 // ---------------------------------------------------------------------------
 // The nodes a level of the general multi-step kernel computes: the slots of
 // its region inside the domain (on a walled axis) and within reach of the
@@ -988,21 +997,22 @@ __device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int
 // the unwritten slots and are discarded.  In tiles at an x wall phase 2 is
 // numbered by columns, so that the nodes next to the wall share few waves.
 // Each node's arithmetic is the single-step kernel's.
+// LDS of the general three-step kernel, in values: the first level's region
+// (odd row pitch TW + 9) and the wall-layer records xs, ys.
+template <int TW, int TH>
+constexpr int step3_wall_lds() { return 13 * (TW + 9) * (TH + 8) + 6 * (TW + TH + 16); }
+
 template <typename R, int TW, int TH, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_per_eu(
-    (13 * (TW + 9) * (TH + 8) + 6 * (TW + TH + 16)) * (int)sizeof(R), NT)))) void step3_wall_kernel(
-    const R* __restrict__ src, R* __restrict__ dst, const Dom<R>* __restrict__ doms, const Tile* __restrict__ tiles,
-    int ntiles, R* __restrict__ side, int from) {
+__device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R* __restrict__ src,
+                                                R* __restrict__ dst, const Dom<R>* __restrict__ doms,
+                                                R* __restrict__ side, int from) {
     constexpr int W1 = TW + 8, H1 = TH + 8, W2 = TW + 4, H2 = TH + 4;
     constexpr int N1 = W1 * H1, N2 = W2 * H2;
     constexpr int P1 = W1 + 1, P2 = W2 + 1;  // odd LDS row pitches: a column is conflict-free
     static_assert(W1 <= 80 && H1 <= 80 && ((N1 + NT - 1) / NT) * NT <= 4096, "LevelWindow's quotient range");
     constexpr int NI1 = (N1 + NT - 1) / NT, NI2 = (N2 + NT - 1) / NT;
-    __shared__ R lds[13 * H1 * P1];
-    __shared__ R xs[2 * H1 * 3];
-    __shared__ R ys[2 * W1 * 3];
-    const int t = xcd_tile(blockIdx.x, ntiles);
-    const Tile tl = tiles[t];
+    R* xs = lds + 13 * H1 * P1;  // [2][H1][3]
+    R* ys = xs + 2 * H1 * 3;     // [2][W1][3]
     const Dom<R>& D = doms[tl.dom];
     const R* __restrict__ a = src + D.off;
     R* __restrict__ o = dst + D.off;
@@ -1101,6 +1111,34 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(lds_waves_pe
         record_wall_layers(side, D, 1 - from, X, Y, q);
     }
 }
+
+template <typename R, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    lds_waves_per_eu(step3_wall_lds<TW, TH>() * (int)sizeof(R), NT)))) void step3_wall_kernel(
+    const R* __restrict__ src, R* __restrict__ dst, const Dom<R>* __restrict__ doms, const Tile* __restrict__ tiles,
+    int ntiles, R* __restrict__ side, int from) {
+    __shared__ R lds[step3_wall_lds<TW, TH>()];
+    const Tile tl = tiles[xcd_tile(blockIdx.x, ntiles)];
+    step3_wall_tile<R, TW, TH, NT>(lds, tl, src, dst, doms, side, from);
+}
+
+// Three steps per launch over a tile table in its spatial order, each tile on
+// the window path (flag 2: an interior tile) or the general path in the one
+// launch: neighbouring tiles run close together in time, so the halo rows they
+// share are read once, and no second kernel runs beside the first.  The LDS is
+// the general path's (the larger); the window path uses its start.
+template <typename R, int TW, int TH, int NT, bool Sourced>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    lds_waves_per_eu(step3_wall_lds<TW, TH>() * (int)sizeof(R), NT)))) void step3_mixed_kernel(
+    const R* __restrict__ src, R* __restrict__ dst, const Dom<R>* __restrict__ doms, const Tile* __restrict__ tiles,
+    int ntiles, R* __restrict__ side, int from) {
+    static_assert(step3_wall_lds<TW, TH>() >= step3_window_lds<TW, TH>(), "the general path's LDS is the larger");
+    __shared__ R lds[step3_wall_lds<TW, TH>()];
+    const Tile tl = tiles[xcd_tile(blockIdx.x, ntiles)];
+    if (tl.flags & 2) step3_window_tile<R, TW, TH, NT, Sourced>(lds, tl, src, dst, doms);
+    else step3_wall_tile<R, TW, TH, NT>(lds, tl, src, dst, doms, side, from);
+}
+
 
 // ---------------------------------------------------------------------------
 // Initial state: g = f^eq(rho, j = rho u, E = T + 13/2 |u|^2) - f^rest, built in
@@ -1615,14 +1653,25 @@ hipError_t launch_step2(int tw, int th, const R* src, R* dst, const Dom<R>* doms
 // Three steps per launch: interior tiles tiles[0, nint) (flag 2, plus 4 where
 // the region wraps) on step3_kernel, the other tiles tiles[nint, nint + nedge)
 // on step3_wall_kernel; sourced = false when no domain has a body force or an
-// energy source.
+// energy source.  mixed: the nint + nedge tiles in their spatial order, each
+// on its path, in one launch of step3_mixed_kernel.
 template <typename R>
 hipError_t launch_step3(int tw, int th, const R* src, R* dst, const Dom<R>* doms, const Tile* tiles, int nint,
-                        int nedge, R* side, int from, bool sourced, hipStream_t s) {
+                        int nedge, R* side, int from, bool sourced, hipStream_t s, bool mixed) {
 #define LBM13_STEP3(T, TW, TH)                                                                                 \
     if constexpr (std::is_same<R, T>::value) {                                                                 \
         if (tw == TW && th == TH) {                                                                            \
             constexpr int NT = sizeof(R) == 4 ? (TW * TH < 256 ? 256 : TW * TH) : (TW * TH >= 512 ? 512 : 256); \
+            if (mixed) {                                                                                       \
+                if (nint + nedge == 0) return hipSuccess;                                                      \
+                if (sourced)                                                                                   \
+                    step3_mixed_kernel<R, TW, TH, NT, true>                                                    \
+                        <<<nint + nedge, NT, 0, s>>>(src, dst, doms, tiles, nint + nedge, side, from);         \
+                else                                                                                           \
+                    step3_mixed_kernel<R, TW, TH, NT, false>                                                   \
+                        <<<nint + nedge, NT, 0, s>>>(src, dst, doms, tiles, nint + nedge, side, from);         \
+                return hipGetLastError();                                                                      \
+            }                                                                                                  \
             if (nint > 0 && sourced)                                                                           \
                 step3_kernel<R, TW, TH, NT, true><<<nint, NT, 0, s>>>(src, dst, doms, tiles, nint);            \
             else if (nint > 0)                                                                                 \
@@ -1752,7 +1801,7 @@ hipError_t launch_ckpt_header(const CkptHeader& h, void* dst, hipStream_t s) {
     template hipError_t launch_step2<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int,     \
                                         hipStream_t);                                                             \
     template hipError_t launch_step3<R>(int, int, const R*, R*, const Dom<R>*, const Tile*, int, int, R*, int,     \
-                                        bool, hipStream_t);                                                       \
+                                        bool, hipStream_t, bool);                                                 \
     template hipError_t launch_side_fill<R>(const R*, const Dom<R>*, const WallLine*, int, R*, int, int,          \
                                             hipStream_t);                                                         \
     template hipError_t launch_diag<R>(int, int, const R*, const Dom<R>*, int, const Tile*, int, double*, R*,     \

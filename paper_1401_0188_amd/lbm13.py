@@ -230,15 +230,17 @@ class _Base:
     _prefix = ""
 
     def launch_config(self) -> dict:
-        """{steps_per_launch, tile (single-step), fused_tile (two-step),
-        interior_kernel (two-step interior tiles on their own kernel)}."""
+        """{steps_per_launch, tile (single-step), fused_tile (two- and three-step),
+        interior_kernel: 0 every multi-step tile on the general kernel, 1 interior
+        tiles on their own kernel beside it, 2 (three steps) both in one launch}."""
         cfg = (ctypes.c_int * 6)()
         self._check(getattr(lib(), self._prefix + "launch_config")(self._h, cfg))
         return dict(steps_per_launch=cfg[0], tile=(cfg[1], cfg[2]), fused_tile=(cfg[3], cfg[4]),
-                    interior_kernel=bool(cfg[5]))
+                    interior_kernel=int(cfg[5]))
 
-    def set_interior_kernel(self, on: bool):
-        self._check(getattr(lib(), self._prefix + "set_interior_kernel")(self._h, int(bool(on))))
+    def set_interior_kernel(self, mode):
+        """0 (False), 1 (True) or 2: see lbm13_set_interior_kernel."""
+        self._check(getattr(lib(), self._prefix + "set_interior_kernel")(self._h, int(mode)))
 
     # The library works on the context's stream; tensors cross between it and
     # the caller's current stream here.  Both helpers do nothing when the two

@@ -382,7 +382,7 @@ def launch_candidates(lbm13, precision):
         for on in (True, False):
             out.append(dict(spl=2, fused_tile=ft, interior_kernel=on))
     for ft in lbm13.STEP3_TILE_SHAPES[precision]:
-        for on in (True, False):
+        for on in (True, False, 2):
             out.append(dict(spl=3, fused_tile=ft, interior_kernel=on))
     return out
 
@@ -696,7 +696,7 @@ def test_contexts_on_separate_streams_are_independent():
     b.destroy()
 
 
-@pytest.mark.parametrize("interior", [True, False])
+@pytest.mark.parametrize("interior", [True, False, 2])
 def test_batched_graph_replays_match_direct_launches(interior):
     """A batch in three-step launches captured in graphs (with the interior
     kernel on, each launch forks onto a second stream and joins back inside
@@ -1603,11 +1603,12 @@ def test_three_steps_per_launch_streaming_is_bit_exact():
             lat.destroy()
 
 
-@pytest.mark.parametrize("interior", [True, False])
+@pytest.mark.parametrize("interior", [True, False, 2])
 @pytest.mark.parametrize("workload", ["cavities64", "channels128"])
 def test_three_steps_per_launch_batched_full_size(workload, interior):
     """The full batches in the benchmark's three-step configurations (interior
-    tiles on the window kernel or every tile on the general kernel)."""
+    tiles on the window kernel beside the general kernel, every tile on the
+    general kernel, or both kinds of tile in one launch)."""
     lbm13 = _lb()
     import bench
     specs = bench.cavity_specs() if workload == "cavities64" else bench.channel_specs()
@@ -1654,15 +1655,17 @@ def test_interior_kernel_switch_is_bit_exact(precision):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_three_step_interior_kernel_switch(precision):
     """Three-step launches with the interior tiles on the window kernel (run
-    concurrently with the general kernel) and with every tile on the general
-    kernel: identical bits with collisions off, equal to rounding with them
-    on, on a domain with walls on y, ragged edges and interior tiles."""
+    concurrently with the general kernel), with every tile on the general
+    kernel, and with both kinds of tile in one launch (mode 2): identical bits
+    with collisions off, equal to rounding with them on, on a domain with walls
+    on y, ragged edges and interior tiles; mode 2 gives the bits of mode 1
+    (each tile runs the same code on the same path)."""
     lbm13 = _lb()
     fields = workloads.shear_acoustic(203, 93)
     sides = lbm13.make_sides((0, 0, 2, 1), (0, 0, 0.02, -0.01), (0, 0, -1.99, 0))
     for collide in (0, 1):
         states = []
-        for on in (True, False):
+        for on in (True, False, 2):
             say("three-step interior kernel %s precision %d collide %d" % (on, precision, collide))
             lat = lbm13.Lattice(203, 93, precision)
             lat.set_fused_tile(32, 16)
@@ -1674,6 +1677,7 @@ def test_three_step_interior_kernel_switch(precision):
             lat.step(24)
             states.append(lat.get_state().cpu().numpy())
             lat.destroy()
+        assert np.array_equal(states[2], states[0])
         if collide == 0:
             assert np.array_equal(states[0], states[1])
         else:
