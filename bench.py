@@ -264,14 +264,14 @@ def build_batch(specs, precision):
     return b
 
 
-def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=True, launch=None):
+def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=True, launch=None, tune_steps=40):
     """`launch`: a fixed launch configuration (a `launch` object of an earlier run) instead of autotuning."""
     import torch
     b = build_batch(specs, precision)
     cfg = dict(launch) if launch else None
     if autotune or cfg:
         if not cfg:
-            b.autotune(10)
+            b.autotune(tune_steps)
             cfg = b.launch_config()
             b.destroy()
             b = build_batch(specs, precision)  # fresh state after tuning
@@ -557,7 +557,8 @@ def main_batched(args, copy_gbps):
     specs = cavity_specs() if args.workload == "cavities64" else channel_specs()
     graph_k = 0 if args.no_graph else GRAPH_K
     log("%s: %d domains, batched fp32-deviation, %d steps" % (args.workload, len(specs), args.steps))
-    r32 = run_batch(specs, lbm13.FP32_DEV, args.steps, args.warmup, args.diag_every, graph_k, launch=args.launch_fp32)
+    r32 = run_batch(specs, lbm13.FP32_DEV, args.steps, args.warmup, args.diag_every, graph_k, launch=args.launch_fp32,
+                    tune_steps=args.tune_steps)
     log("batched fp32: %.1f MLUPS, kernel %.4f ms per launch, config %s" % (r32["mlups"], r32["kernel_ms_per_launch"],
                                                                           r32["cfg"]))
     fp64_steps = args.fp64_steps if args.fp64_steps >= 0 else max(1, args.steps // 4)
@@ -783,7 +784,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the error report (timed forms against the oracle and FP32 against FP64)")
     ap.add_argument("--tune-steps", type=int, default=40,
-                    help="steps per candidate of the launch autotuner for the wave forms (0: fixed configuration)")
+                    help="steps per candidate of the launch autotuner (0: fixed configuration for the wave forms)")
     ap.add_argument("--launch-fp32", type=json.loads, metavar="JSON",
                     help="fix the FP32 launch configuration (a `launch` object of an earlier run; no autotuning); "
                          "also for the batched workloads")
