@@ -225,8 +225,8 @@ int lbm13_autotune(lbm13_ctx *ctx, int steps, int *tile_x, int *tile_y);
 int lbm13_autotune_cached(lbm13_ctx *ctx, int steps, const char *cache_path, int *from_cache);
 
 /* Current launch configuration: cfg = {steps per launch, single-step tile_x,
- * tile_y, two- and three-step tile_x, tile_y, interior kernel on (1) or off
- * (0)}.
+ * tile_y, two- and three-step tile_x, tile_y, interior-kernel mode 0, 1 or 2
+ * (lbm13_set_interior_kernel)}.
  * Host-only. */
 int lbm13_launch_config(const lbm13_ctx *ctx, int cfg[6]);
 

@@ -930,11 +930,12 @@ C4_ORACLE_DOMAINS = (62, 33, 58, 19, 23, 8)
 _C4_ORACLE = {}
 
 
-@pytest.mark.parametrize("interior", [1, 0])
+@pytest.mark.parametrize("interior", [1, 0, 2])
 def test_cavities64_full_batch_10k_steps_oracle_parity(interior):
     """The 64-cavity batch (every domain, FP32 deviation form) in the
-    benchmark's three-step 32x16 launches, with and without the interior-tile
-    kernel, in HIP graphs of 120 steps, for 10^4 steps (the horizon of the
+    benchmark's three-step 32x16 launches, with the interior tiles on the
+    window kernel beside the general kernel, every tile on the general kernel,
+    and both kinds in one launch, in HIP graphs of 120 steps, for 10^4 steps (the horizon of the
     FP32 bound): the worst-conditioned cavities against the FP64 oracle within
     1e-5 absolute on rho, u and T (the FP32 measure), and every domain finite."""
     lbm13 = _lb()
@@ -1033,7 +1034,8 @@ def test_channel_profiles_match_startup_series():
 def test_benchmark_channels_50000_steps():
     """The 128 channels of the benchmark (W 32-256 with temperature walls, L
     256-2048 periodic, half Couette, half Poiseuille; started from rest) in the
-    benchmark's three-step launch for 5 x 10^4 steps.  A channel stays uniform
+    benchmark's three-step launch (32x16, both kinds of tile in one launch, the
+    autotuner's choice for this batch) for 5 x 10^4 steps.  A channel stays uniform
     along y, so each of its rows equals the oracle's run on a periodic strip of
     4 rows with the same width and parameters: every ninth channel is compared
     with that run at the FP32 bar (rho, u, T), every channel is checked to be
@@ -1049,7 +1051,7 @@ def test_benchmark_channels_50000_steps():
         ders.append(b.set_params(i, sides=lbm13.make_sides(*s["sides"]), **s["kw"]))
         b.init_moments(i, *bench.spec_fields(s))
     b.set_fused_tile(32, 16)
-    b.set_interior_kernel(False)
+    b.set_interior_kernel(2)
     b.set_steps_per_launch(3)
     b.use_graph(120)
     steps = 50000
