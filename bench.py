@@ -36,6 +36,7 @@ BENCH_CONFIG = {1: dict(spl=3, fused_tile=(64, 16), tile=(64, 8), interior_kerne
                 0: dict(spl=3, fused_tile=(32, 16), tile=(64, 8), interior_kernel=True)}
 BENCH_TILE = BENCH_CONFIG[1]["tile"]
 GRAPH_K = 120                 # steps per captured HIP graph (a multiple of 2 and 3: whole multi-step launches)
+SETTLE_STEPS = 240            # set-up: steps of the chosen launches run before the state restarts
 ACCURACY_STEPS = 10000        # FP32 against FP64 on the GPU after this many steps (the stated FP32 bound's horizon)
 BYTES_PER_LU = {0: 208, 1: 104}  # 13 loads + 13 stores of populations, FP64 / FP32
 HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E
@@ -134,6 +135,13 @@ def graph_length(graph_k, steps, spl):
     return steps // unit * unit if steps >= unit else 0
 
 
+def settle_steps(gk, spl):
+    """Set-up steps before timing: SETTLE_STEPS rounded up to whole graph
+    replays (or whole launches without a graph)."""
+    unit = gk if gk else spl
+    return max(unit, -(-SETTLE_STEPS // unit) * unit)
+
+
 def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0):
     """Time one form on the n x n wave.  cfg fixes the launch configuration;
     tune_steps > 0 lets the library's autotuner pick it on this device instead
@@ -161,11 +169,12 @@ def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0
     spl = launch["steps_per_launch"]
     gk = graph_length(graph_k, steps, spl)
     if gk:
-        # set-up, like the autotuning: capture the graph (an even number of
-        # launches, so one capture serves) and start again from the initial state
-        lat.use_graph(gk)
-        lat.step(gk)
-        lat.load(initial)
+        lat.use_graph(gk)  # an even number of launches, so one capture serves
+    # set-up, like the autotuning: run the chosen launches for a few hundred steps
+    # (a graph's first replay uploads it, and the GPU's clock rises under sustained
+    # load over tens of milliseconds), then start again from the initial state
+    lat.step(settle_steps(gk, spl))
+    lat.load(initial)
     del initial
     lat.step(warmup)
     d0 = lat.diagnostics()
@@ -281,6 +290,12 @@ def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=Tru
         b.set_steps_per_launch(cfg["steps_per_launch"])
     if graph_k:
         b.use_graph(graph_k)
+    # set-up as for one domain: run the chosen launches, then restore every domain
+    saved = [b.save(i) for i in range(b.count)]
+    b.step(settle_steps(graph_k, cfg["steps_per_launch"] if cfg else 1))
+    for i, blob in enumerate(saved):
+        b.load(i, blob)
+    del saved
     b.step(warmup)
     b.diagnostics()
     torch.cuda.synchronize()

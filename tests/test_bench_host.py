@@ -109,3 +109,13 @@ def test_graph_length_is_whole_even_launches(graph_k, steps, spl, expect):
     assert gk == expect
     if gk:
         assert gk % spl == 0 and (gk // spl) % 2 == 0 and gk <= steps
+
+
+@pytest.mark.parametrize("gk,spl,expect", [(120, 3, 240), (18, 3, 252), (0, 3, 240), (0, 2, 240), (0, 1, 240),
+                                           (4096, 3, 4096)])
+def test_settle_steps_are_whole_replays(gk, spl, expect):
+    """The set-up before timing runs whole graph replays (or whole launches
+    without a graph), at least SETTLE_STEPS steps."""
+    k = bench.settle_steps(gk, spl)
+    assert k == expect and k >= bench.SETTLE_STEPS
+    assert k % (gk if gk else spl) == 0
