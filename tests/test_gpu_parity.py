@@ -831,6 +831,20 @@ def test_autotune_cache_round_trip(tmp_path):
     assert json.load(open(path))["entries"]
     c.step(6)
     assert c.diagnostics()["nonfinite"] == 0
+    # an entry with both kinds of three-step tile in one launch (mode 2) is
+    # applied as stored; a mode this build does not know is tuned again
+    key = list(json.load(open(path))["entries"])[0]
+    for mode, hit in ((2, True), (3, False)):
+        with open(path, "w") as fh:
+            json.dump({"version": 1, "entries": {key: [3, 64, 8, 32, 16, mode]}}, fh)
+        d = ctx()
+        assert d.autotune_cached(path, steps=6) is hit
+        if hit:
+            got = d.launch_config()
+            assert (got["steps_per_launch"], got["fused_tile"], got["interior_kernel"]) == (3, (32, 16), 2)
+        d.step(6)
+        assert d.diagnostics()["nonfinite"] == 0
+        d.destroy()
     for lat in (a, b, c):
         lat.destroy()
 
