@@ -173,7 +173,8 @@ def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0
     # set-up, like the autotuning: run the chosen launches for a few hundred steps
     # (a graph's first replay uploads it, and the GPU's clock rises under sustained
     # load over tens of milliseconds), then start again from the initial state
-    lat.step(settle_steps(gk, spl))
+    setup = settle_steps(gk, spl)
+    lat.step(setup)
     lat.load(initial)
     del initial
     lat.step(warmup)
@@ -211,7 +212,7 @@ def run_form(precision, n, steps, warmup, diag_every, cfg, graph_k, tune_steps=0
     torch.cuda.empty_cache()
     return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=per_launch,
                 mlups=nodes * steps / wall / 1e6, kernel_mlups=nodes / (kern_ms / steps * 1e-3) / 1e6,
-                mass_drift=drift, nodes=nodes, spl=spl, launch=launch, graph_steps=gk)
+                mass_drift=drift, nodes=nodes, spl=spl, launch=launch, graph_steps=gk, setup_steps=setup)
 
 
 def cavity_specs(count=64, seed=4):
@@ -292,7 +293,8 @@ def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=Tru
         b.use_graph(graph_k)
     # set-up as for one domain: run the chosen launches, then restore every domain
     saved = [b.save(i) for i in range(b.count)]
-    b.step(settle_steps(graph_k, cfg["steps_per_launch"] if cfg else 1))
+    setup = settle_steps(graph_k, cfg["steps_per_launch"] if cfg else 1)
+    b.step(setup)
     for i, blob in enumerate(saved):
         b.load(i, blob)
     del saved
@@ -322,7 +324,7 @@ def run_batch(specs, precision, steps, warmup, diag_every, graph_k, autotune=Tru
     torch.cuda.empty_cache()
     spl = cfg["steps_per_launch"] if cfg else 1
     return dict(wall_s=wall, ms_per_step=wall * 1e3 / steps, kernel_ms_per_launch=kern_ms / steps * spl,
-                mlups=nodes * steps / wall / 1e6, nodes=nodes, cfg=cfg, spl=spl, diag=diag)
+                mlups=nodes * steps / wall / 1e6, nodes=nodes, cfg=cfg, spl=spl, diag=diag, setup_steps=setup)
 
 
 def run_sequential_fp64(specs, steps):
@@ -618,7 +620,8 @@ def main_batched(args, copy_gbps):
         "config": {"workload": "%s: %d domains, %d nodes" % (args.workload, len(specs), r32["nodes"]),
                    "form": "fp32-deviation batched, one launch covers every domain", "launch": r32["cfg"],
                    "launch_choice": "fixed" if args.launch_fp32 else "autotuned on this device",
-                   "graph_steps": graph_k, "diag_every": args.diag_every, "clamped_domains": clamped},
+                   "graph_steps": graph_k, "diag_every": args.diag_every, "clamped_domains": clamped,
+                   "setup_steps": r32["setup_steps"]},
         "roofline": roofline(r32["nodes"], r32["kernel_ms_per_launch"], 1, spl=r32["spl"], sourced=True,
                              traffic=measured_traffic(args.workload, r32["cfg"], BATCH_TRAFFIC_FILE) if r32["cfg"] else None,
                              counters=measured_counters(args.workload, r32["cfg"], BATCH_TRAFFIC_FILE)
@@ -895,7 +898,8 @@ def main():
         "config": {"workload": "periodic %dx%d transverse shear + acoustic wave" % (n, n), "nx": n, "ny": n,
                    "form": "fp32-deviation", "launch": r32["launch"],
                    "launch_choice": "autotuned on this device" if tune32 else "fixed",
-                   "graph_steps": r32["graph_steps"], "diag_every": args.diag_every},
+                   "graph_steps": r32["graph_steps"], "diag_every": args.diag_every,
+                   "setup_steps": r32["setup_steps"]},
         "roofline": roof32,
         "cpu_baseline": cpu,
         "fp64": {"value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 5),
