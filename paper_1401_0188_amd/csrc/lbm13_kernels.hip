@@ -960,14 +960,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 // (r + 1/2) / w from an integer, 1 / (2w), exceeds the rounding error).
 struct LevelWindow {
     int x0, y0, w, h, n;
-    bool col;   // numbered column by column instead: a wave then takes 64 / h
-                // columns, so the nodes next to an x wall fall into one or two
-                // waves and only those run the wall fix-ups
-    float inv;  // 1 / w, or 1 / h by columns
+    float inv;  // 1 / w
     __device__ __forceinline__ void slot(int r, int& lx, int& ly) const {
-        const int q = (int)(((float)r + 0.5f) * inv), m = r - q * (col ? h : w);
-        lx = x0 + (col ? q : m);
-        ly = y0 + (col ? m : q);
+        const int q = (int)(((float)r + 0.5f) * inv);
+        lx = x0 + r - q * w;
+        ly = y0 + q;
     }
 };
 
@@ -977,7 +974,7 @@ template <typename R>
 __device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int oy, int ex, int ey) {
     const int xa = D.xper ? 0 : max(0, -ox), xb = D.xper ? ex : min(ex, D.nx - ox);
     const int ya = D.yper ? 0 : max(0, -oy), yb = D.yper ? ey : min(ey, D.ny - oy);
-    return LevelWindow{xa, ya, xb - xa, yb - ya, (xb - xa) * (yb - ya), false, 1.0f / (float)(xb - xa)};
+    return LevelWindow{xa, ya, xb - xa, yb - ya, (xb - xa) * (yb - ya), 1.0f / (float)(xb - xa)};
 }
 
 // ---------------------------------------------------------------------------
@@ -988,19 +985,73 @@ __device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int
 // advances the (TW + 8) x (TH + 8) region from HBM (wall fix-ups from the side
 // array of step t), phase 2 the (TW + 4) x (TH + 4) region from LDS into
 // registers (wall fix-ups from the layer values phase 1 kept), then, after a
-// barrier, stores it and its layer values over the first level; phase 3
-// advances the tile, writes HBM and the side array of step t + 3.  Each level
-// computes only the window of its region inside the domain and within reach
-// of the tile's nodes (LevelWindow); region slots beyond a wall are never
-// written.  Phases 2 and 3 read every node's sources with the plain stencil,
-// then replace the links from beyond a wall (wall_fixups): those reads land in
-// the unwritten slots and are discarded.  In tiles at an x wall phase 2 is
-// numbered by columns, so that the nodes next to the wall share few waves.
-// Each node's arithmetic is the single-step kernel's.
-// LDS of the general three-step kernel, in values: the first level's region
-// (odd row pitch TW + 9) and the wall-layer records xs, ys.
+// barrier, keeps it and its layer values for phase 3; phase 3 advances the
+// tile, writes HBM and the side array of step t + 3.  Each level computes only
+// the window of its region inside the domain and within reach of the tile's
+// nodes (LevelWindow); slots beyond a wall are never written.  A level keeps
+// population i in LDS over the slots the next level reads (WallWindows), and
+// phases 2 and 3 read every node's sources with the plain stencil, then
+// replace the links from beyond a wall (wall_fixups): those reads land in the
+// unwritten slots and are discarded.  Each node's arithmetic is the
+// single-step kernel's.
+//
+// WallWindows<W, H, Last>: population i of a level kept over the W x H region
+// of the level that reads it, shifted by -v_i, plus the slots past its edges
+// that the wall fix-ups read for reflected populations (fix_link: the
+// tangential coordinate kept, the normal one mirrored in the wall).  Tiles lie
+// on a grid of whole tiles from the domain's origin, so the second level's
+// region starts two nodes before a West or South wall; a tile can end one,
+// two or three nodes before an East or North wall, whose reflected speed-2
+// sources then lie up to three slots past the region (one for speed 1); a
+// diagonal reflected at a wall moves one slot along it.  The third level's
+// region is the tile itself, whose edge is the West or South wall: population
+// i then needs |v_i| slots on each side v_i points to (three for the speed-2
+// populations on the high sides, as above).  Slot u (relative to the reading
+// level's origin) of population i is at base(i) + (u_y + ylo(i)) w(i) + u_x +
+// xlo(i).
+template <int W, int H, bool Last>
+struct WallWindows {
+    static constexpr int xhi(int i) { return kVX[i] > 0 ? (kVX[i] == 2 ? 3 : 1) : 0; }
+    static constexpr int yhi(int i) { return kVY[i] > 0 ? (kVY[i] == 2 ? 3 : 1) : 0; }
+    static constexpr int xlo(int i) { return kVX[i] < 0 ? (Last ? -kVX[i] : (kVY[i] != 0 ? 1 : 0)) : 0; }
+    static constexpr int ylo(int i) { return kVY[i] < 0 ? (Last ? -kVY[i] : (kVX[i] != 0 ? 1 : 0)) : 0; }
+    static constexpr int w(int i) { return W + xlo(i) + xhi(i); }
+    static constexpr int h(int i) { return H + ylo(i) + yhi(i); }
+    static constexpr int base(int i) {
+        int b = 0;
+        for (int j = 0; j < i; ++j) b += w(j) * h(j);
+        return b;
+    }
+    static constexpr int total() { return base(13); }
+    // the slot of population i that the reading level's node u pulls (or the
+    // fix-ups read), and whether population i of a node keeps slot u
+    static constexpr int at(int i, int ux, int uy) { return base(i) + (uy + ylo(i)) * w(i) + ux + xlo(i); }
+    static constexpr bool keeps(int i, int ux, int uy) {
+        return ux >= -xlo(i) && ux < W + xhi(i) && uy >= -ylo(i) && uy < H + yhi(i);
+    }
+};
+
+// A level's populations in its WallWindows, read by absolute coordinates (of
+// the producing node) for the fix-ups of the level whose region starts at
+// (ox, oy).
+template <typename R, int W, int H, bool Last>
+struct WinSrc {
+    const R* l;
+    int ox, oy;
+    __device__ __forceinline__ R get(int i, int X, int Y) const {
+        return l[WallWindows<W, H, Last>::at(i, X - ox + kVX[i], Y - oy + kVY[i])];
+    }
+};
+
+// LDS of the general three-step kernel, in values: the windows of the second
+// or third level (the larger) and the wall-layer records xs, ys.
 template <int TW, int TH>
-constexpr int step3_wall_lds() { return 13 * (TW + 9) * (TH + 8) + 6 * (TW + TH + 16); }
+constexpr int step3_wall_lds() {
+    return (WallWindows<TW + 4, TH + 4, false>::total() > WallWindows<TW, TH, true>::total()
+                ? WallWindows<TW + 4, TH + 4, false>::total()
+                : WallWindows<TW, TH, true>::total()) +
+           6 * (TW + TH + 16);
+}
 
 template <typename R, int TW, int TH, int NT>
 __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R* __restrict__ src,
@@ -1008,11 +1059,13 @@ __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R*
                                                 R* __restrict__ side, int from) {
     constexpr int W1 = TW + 8, H1 = TH + 8, W2 = TW + 4, H2 = TH + 4;
     constexpr int N1 = W1 * H1, N2 = W2 * H2;
-    constexpr int P1 = W1 + 1, P2 = W2 + 1;  // odd LDS row pitches: a column is conflict-free
     static_assert(W1 <= 80 && H1 <= 80 && ((N1 + NT - 1) / NT) * NT <= 4096, "LevelWindow's quotient range");
     constexpr int NI1 = (N1 + NT - 1) / NT, NI2 = (N2 + NT - 1) / NT;
-    R* xs = lds + 13 * H1 * P1;  // [2][H1][3]
-    R* ys = xs + 2 * H1 * 3;     // [2][W1][3]
+    using Win2 = WallWindows<W2, H2, false>;  // the first level's populations, read by the second
+    using Win3 = WallWindows<TW, TH, true>;   // the second level's, read by the tile
+    constexpr int NW = Win2::total() > Win3::total() ? Win2::total() : Win3::total();
+    R* xs = lds + NW;         // [2][H1][3]
+    R* ys = xs + 2 * H1 * 3;  // [2][W1][3]
     const Dom<R>& D = doms[tl.dom];
     const R* __restrict__ a = src + D.off;
     R* __restrict__ o = dst + D.off;
@@ -1051,7 +1104,10 @@ __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R*
         const int lx = l1x[k], ly = l1y[k];
         if (D.collide) collide(g[k], D);
 #pragma unroll
-        for (int i = 0; i < 13; ++i) lds[(i * H1 + ly) * P1 + lx] = g[k][i];
+        for (int i = 0; i < 13; ++i) {
+            const int ux = lx - 2 + kVX[i], uy = ly - 2 + kVY[i];  // the second-level slot that pulls it
+            if (Win2::keeps(i, ux, uy)) lds[Win2::at(i, ux, uy)] = g[k][i];
+        }
         record_region_layers<R, W1, H1>(xs, ys, D, X1[k], Y1[k], lx, ly, g[k]);
     }
     __syncthreads();
@@ -1060,13 +1116,11 @@ __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R*
     // (coordinates unwrapped on periodic axes, as the region stores them).
     // The plain stencil's reads are those of gather_wall for every link it
     // keeps, so the result is the same.
-    const LdsSrc<R, P1, H1> L1{lds, o1x, o1y, D.nx, D.ny, D.xper, D.yper};
+    const WinSrc<R, W2, H2, false> L1{lds, o2x, o2y};
     const LdsSide<R, W1, H1> S1{xs, ys, o1x, o1y};
     const bool walls2 =
         (!D.xper && (o2x < 2 || o2x + W2 > D.nx - 2)) || (!D.yper && (o2y < 2 || o2y + H2 > D.ny - 2));
-    const bool xwall2 = !D.xper && (o2x < 2 || o2x + W2 > D.nx - 2);
-    const LevelWindow r2 = level_window(D, o2x, o2y, tw3 + 4, th3 + 4);
-    const LevelWindow w2{r2.x0, r2.y0, r2.w, r2.h, r2.n, xwall2, xwall2 ? 1.0f / (float)r2.h : r2.inv};
+    const LevelWindow w2 = level_window(D, o2x, o2y, tw3 + 4, th3 + 4);
     R h[NI2][13];
     int l2x[NI2], l2y[NI2];
     bool v2[NI2];
@@ -1077,7 +1131,7 @@ __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R*
         v2[k] = tid + k * NT < w2.n;
         if (!v2[k]) continue;
 #pragma unroll
-        for (int i = 0; i < 13; ++i) h[k][i] = lds[(i * H1 + ly + 2 - kVY[i]) * P1 + lx + 2 - kVX[i]];
+        for (int i = 0; i < 13; ++i) h[k][i] = lds[Win2::at(i, lx, ly)];
         if (walls2) wall_fixups(L1, S1, D, X, Y, h[k]);
         if (D.collide) collide(h[k], D);
     }
@@ -1087,24 +1141,27 @@ __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R*
         if (!v2[k]) continue;
         const int lx = l2x[k], ly = l2y[k];
 #pragma unroll
-        for (int i = 0; i < 13; ++i) lds[(i * H2 + ly) * P2 + lx] = h[k][i];
+        for (int i = 0; i < 13; ++i) {
+            const int ux = lx - 2 + kVX[i], uy = ly - 2 + kVY[i];  // the tile slot that pulls it
+            if (Win3::keeps(i, ux, uy)) lds[Win3::at(i, ux, uy)] = h[k][i];
+        }
         record_region_layers<R, W2, H2>(xs, ys, D, o2x + lx, o2y + ly, lx, ly, h[k]);
     }
     __syncthreads();
 
     // Phase 3: t + 2 -> t + 3 over the tile, gathers from the second level.
-    const LdsSrc<R, P2, H2> L2{lds, o2x, o2y, D.nx, D.ny, D.xper, D.yper};
+    const WinSrc<R, TW, TH, true> L2{lds, tl.x0, tl.y0};
     const LdsSide<R, W2, H2> S2{xs, ys, o2x, o2y};
     const bool walls3 = (!D.xper && (tl.x0 < 2 || tl.x0 + TW > D.nx - 2)) ||
                         (!D.yper && (tl.y0 < 2 || tl.y0 + TH > D.ny - 2));
-    const LevelWindow w3{2, 2, tw3, th3, tw3 * th3, false, 1.0f / (float)tw3};
+    const LevelWindow w3{2, 2, tw3, th3, tw3 * th3, 1.0f / (float)tw3};
     for (int r = tid; r < w3.n; r += NT) {
         int lx, ly;
         w3.slot(r, lx, ly);
         const int X = o2x + lx, Y = o2y + ly;
         R q[13];
 #pragma unroll
-        for (int i = 0; i < 13; ++i) q[i] = lds[(i * H2 + ly - kVY[i]) * P2 + lx - kVX[i]];
+        for (int i = 0; i < 13; ++i) q[i] = lds[Win3::at(i, lx - 2, ly - 2)];
         if (walls3) wall_fixups(L2, S2, D, X, Y, q);
         if (D.collide) collide(q, D);
         store_node(o, D.plane, Y * D.pitch + X, q);
