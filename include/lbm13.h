@@ -241,7 +241,8 @@ int lbm13_use_graph(lbm13_ctx *ctx, int k);
  * 2-node halo, then the tile: a third of the HBM traffic per step; any sides
  * and walls, wall states of the intermediate steps from the levels kept in
  * LDS; tiles far from walls and ragged edges run a kernel that keeps only the
- * windows the next level reads, the others keep each level's whole region;
+ * windows the next level reads, the others also keep the slots the wall
+ * fix-ups read for reflected populations;
  * the two-step tile must be a three-step shape: FP32 (64, 16), (32, 32),
  * (64, 8), (32, 16), (32, 8); FP64 (64, 8), (32, 16), (32, 8); lbm13_step returns
  * EINVAL otherwise).  A remainder of lbm13_step(n) is done by shorter

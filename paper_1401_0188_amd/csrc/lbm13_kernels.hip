@@ -980,10 +980,10 @@ __device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int
 // ---------------------------------------------------------------------------
 // Three steps per launch on the other tiles: tiles that reach a wall (their
 // region, a tile plus four nodes on each side, or its gathers), a ragged
-// domain edge or a periodic axis shorter than the region.  The state of each
-// level is kept over its whole region in LDS, as in step2_kernel: phase 1
-// advances the (TW + 8) x (TH + 8) region from HBM (wall fix-ups from the side
-// array of step t), phase 2 the (TW + 4) x (TH + 4) region from LDS into
+// domain edge or a periodic axis shorter than the region.  Each level's
+// result is kept in LDS for the next (WallWindows, below): phase 1 advances
+// the (TW + 8) x (TH + 8) region from HBM (wall fix-ups from the side array of
+// step t), phase 2 the (TW + 4) x (TH + 4) region from LDS into
 // registers (wall fix-ups from the layer values phase 1 kept), then, after a
 // barrier, keeps it and its layer values for phase 3; phase 3 advances the
 // tile, writes HBM and the side array of step t + 3.  Each level computes only
@@ -997,14 +997,15 @@ __device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int
 //
 // WallWindows<W, H, Last>: population i of a level kept over the W x H region
 // of the level that reads it, shifted by -v_i, plus the slots past its edges
-// that the wall fix-ups read for reflected populations (fix_link: the
+// that the wall fix-ups read for reflected populations (fix_link, sec. 7: the
 // tangential coordinate kept, the normal one mirrored in the wall).  Tiles lie
 // on a grid of whole tiles from the domain's origin, so the second level's
 // region starts two nodes before a West or South wall; a tile can end one,
 // two or three nodes before an East or North wall, whose reflected speed-2
 // sources then lie up to three slots past the region (one for speed 1); a
 // diagonal reflected at a wall moves one slot along it.  The third level's
-// region is the tile itself, whose edge is the West or South wall: population
+// region is the tile itself, whose low edge can be the West or South wall, and
+// which can end one to three nodes before the East or North wall: population
 // i then needs |v_i| slots on each side v_i points to (three for the speed-2
 // populations on the high sides, as above).  Slot u (relative to the reading
 // level's origin) of population i is at base(i) + (u_y + ylo(i)) w(i) + u_x +
