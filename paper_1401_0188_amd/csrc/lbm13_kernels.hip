@@ -960,21 +960,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 // (r + 1/2) / w from an integer, 1 / (2w), exceeds the rounding error).
 struct LevelWindow {
     int x0, y0, w, h, n;
-    float inv;  // 1 / w
+    bool col;   // numbered column by column instead (the general kernel's second
+                // level in tiles at an x wall: a wave then takes a few columns,
+                // so the nodes next to the wall fall into one or two waves)
+    float inv;  // 1 / w, or 1 / h by columns
     __device__ __forceinline__ void slot(int r, int& lx, int& ly) const {
-        const int q = (int)(((float)r + 0.5f) * inv);
-        lx = x0 + r - q * w;
-        ly = y0 + q;
+        const int q = (int)(((float)r + 0.5f) * inv), m = r - q * (col ? h : w);
+        lx = x0 + (col ? q : m);
+        ly = y0 + (col ? m : q);
     }
 };
 
 // Window of a level whose region starts at (ox, oy) and whose tile's nodes
 // reach ex columns and ey rows of it.
 template <typename R>
-__device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int oy, int ex, int ey) {
+__device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int oy, int ex, int ey, bool col = false) {
     const int xa = D.xper ? 0 : max(0, -ox), xb = D.xper ? ex : min(ex, D.nx - ox);
     const int ya = D.yper ? 0 : max(0, -oy), yb = D.yper ? ey : min(ey, D.ny - oy);
-    return LevelWindow{xa, ya, xb - xa, yb - ya, (xb - xa) * (yb - ya), 1.0f / (float)(xb - xa)};
+    return LevelWindow{xa, ya, xb - xa, yb - ya, (xb - xa) * (yb - ya), col,
+                       col ? 1.0f / (float)(yb - ya) : 1.0f / (float)(xb - xa)};
 }
 
 // ---------------------------------------------------------------------------
@@ -1009,14 +1013,14 @@ __device__ __forceinline__ LevelWindow level_window(const Dom<R>& D, int ox, int
 // i then needs |v_i| slots on each side v_i points to (three for the speed-2
 // populations on the high sides, as above).  Slot u (relative to the reading
 // level's origin) of population i is at base(i) + (u_y + ylo(i)) w(i) + u_x +
-// xlo(i).
-template <int W, int H, bool Last>
+// xlo(i), w(i) the window's width, made odd when Odd.
+template <int W, int H, bool Last, bool Odd = false>
 struct WallWindows {
     static constexpr int xhi(int i) { return kVX[i] > 0 ? (kVX[i] == 2 ? 3 : 1) : 0; }
     static constexpr int yhi(int i) { return kVY[i] > 0 ? (kVY[i] == 2 ? 3 : 1) : 0; }
     static constexpr int xlo(int i) { return kVX[i] < 0 ? (Last ? -kVX[i] : (kVY[i] != 0 ? 1 : 0)) : 0; }
     static constexpr int ylo(int i) { return kVY[i] < 0 ? (Last ? -kVY[i] : (kVX[i] != 0 ? 1 : 0)) : 0; }
-    static constexpr int w(int i) { return W + xlo(i) + xhi(i); }
+    static constexpr int w(int i) { return (W + xlo(i) + xhi(i)) | (Odd ? 1 : 0); }  // row pitch
     static constexpr int h(int i) { return H + ylo(i) + yhi(i); }
     static constexpr int base(int i) {
         int b = 0;
@@ -1035,24 +1039,34 @@ struct WallWindows {
 // A level's populations in its WallWindows, read by absolute coordinates (of
 // the producing node) for the fix-ups of the level whose region starts at
 // (ox, oy).
-template <typename R, int W, int H, bool Last>
+template <typename R, int W, int H, bool Last, bool Odd>
 struct WinSrc {
     const R* l;
     int ox, oy;
     __device__ __forceinline__ R get(int i, int X, int Y) const {
-        return l[WallWindows<W, H, Last>::at(i, X - ox + kVX[i], Y - oy + kVY[i])];
+        return l[WallWindows<W, H, Last, Odd>::at(i, X - ox + kVX[i], Y - oy + kVY[i])];
     }
 };
 
 // LDS of the general three-step kernel, in values: the windows of the second
 // or third level (the larger) and the wall-layer records xs, ys.
-template <int TW, int TH>
-constexpr int step3_wall_lds() {
-    return (WallWindows<TW + 4, TH + 4, false>::total() > WallWindows<TW, TH, true>::total()
-                ? WallWindows<TW + 4, TH + 4, false>::total()
-                : WallWindows<TW, TH, true>::total()) +
+template <int TW, int TH, bool Odd>
+constexpr int step3_wall_lds_of() {
+    return (WallWindows<TW + 4, TH + 4, false, Odd>::total() > WallWindows<TW, TH, true, Odd>::total()
+                ? WallWindows<TW + 4, TH + 4, false, Odd>::total()
+                : WallWindows<TW, TH, true, Odd>::total()) +
            6 * (TW + TH + 16);
 }
+// Odd row pitches, so that the column-numbered second level reads LDS free of
+// bank conflicts, where they cost no occupancy (not for FP32 32x16, whose
+// even-pitched windows just fit four workgroups per CU).
+template <typename R, int TW, int TH, int NT>
+constexpr bool step3_wall_odd() {
+    return lds_waves_per_eu(step3_wall_lds_of<TW, TH, true>() * (int)sizeof(R), NT) ==
+           lds_waves_per_eu(step3_wall_lds_of<TW, TH, false>() * (int)sizeof(R), NT);
+}
+template <typename R, int TW, int TH, int NT>
+constexpr int step3_wall_lds() { return step3_wall_lds_of<TW, TH, step3_wall_odd<R, TW, TH, NT>()>(); }
 
 template <typename R, int TW, int TH, int NT>
 __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R* __restrict__ src,
@@ -1062,8 +1076,9 @@ __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R*
     constexpr int N1 = W1 * H1, N2 = W2 * H2;
     static_assert(W1 <= 80 && H1 <= 80 && ((N1 + NT - 1) / NT) * NT <= 4096, "LevelWindow's quotient range");
     constexpr int NI1 = (N1 + NT - 1) / NT, NI2 = (N2 + NT - 1) / NT;
-    using Win2 = WallWindows<W2, H2, false>;  // the first level's populations, read by the second
-    using Win3 = WallWindows<TW, TH, true>;   // the second level's, read by the tile
+    constexpr bool Odd = step3_wall_odd<R, TW, TH, NT>();
+    using Win2 = WallWindows<W2, H2, false, Odd>;  // the first level's populations, read by the second
+    using Win3 = WallWindows<TW, TH, true, Odd>;   // the second level's, read by the tile
     constexpr int NW = Win2::total() > Win3::total() ? Win2::total() : Win3::total();
     R* xs = lds + NW;         // [2][H1][3]
     R* ys = xs + 2 * H1 * 3;  // [2][W1][3]
@@ -1117,11 +1132,12 @@ __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R*
     // (coordinates unwrapped on periodic axes, as the region stores them).
     // The plain stencil's reads are those of gather_wall for every link it
     // keeps, so the result is the same.
-    const WinSrc<R, W2, H2, false> L1{lds, o2x, o2y};
+    const WinSrc<R, W2, H2, false, Odd> L1{lds, o2x, o2y};
     const LdsSide<R, W1, H1> S1{xs, ys, o1x, o1y};
     const bool walls2 =
         (!D.xper && (o2x < 2 || o2x + W2 > D.nx - 2)) || (!D.yper && (o2y < 2 || o2y + H2 > D.ny - 2));
-    const LevelWindow w2 = level_window(D, o2x, o2y, tw3 + 4, th3 + 4);
+    const bool xwall2 = Odd && !D.xper && (o2x < 2 || o2x + W2 > D.nx - 2);
+    const LevelWindow w2 = level_window(D, o2x, o2y, tw3 + 4, th3 + 4, xwall2);
     R h[NI2][13];
     int l2x[NI2], l2y[NI2];
     bool v2[NI2];
@@ -1151,11 +1167,11 @@ __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R*
     __syncthreads();
 
     // Phase 3: t + 2 -> t + 3 over the tile, gathers from the second level.
-    const WinSrc<R, TW, TH, true> L2{lds, tl.x0, tl.y0};
+    const WinSrc<R, TW, TH, true, Odd> L2{lds, tl.x0, tl.y0};
     const LdsSide<R, W2, H2> S2{xs, ys, o2x, o2y};
     const bool walls3 = (!D.xper && (tl.x0 < 2 || tl.x0 + TW > D.nx - 2)) ||
                         (!D.yper && (tl.y0 < 2 || tl.y0 + TH > D.ny - 2));
-    const LevelWindow w3{2, 2, tw3, th3, tw3 * th3, 1.0f / (float)tw3};
+    const LevelWindow w3{2, 2, tw3, th3, tw3 * th3, false, 1.0f / (float)tw3};
     for (int r = tid; r < w3.n; r += NT) {
         int lx, ly;
         w3.slot(r, lx, ly);
@@ -1172,10 +1188,10 @@ __device__ __forceinline__ void step3_wall_tile(R* lds, const Tile& tl, const R*
 
 template <typename R, int TW, int TH, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
-    lds_waves_per_eu(step3_wall_lds<TW, TH>() * (int)sizeof(R), NT)))) void step3_wall_kernel(
+    lds_waves_per_eu(step3_wall_lds<R, TW, TH, NT>() * (int)sizeof(R), NT)))) void step3_wall_kernel(
     const R* __restrict__ src, R* __restrict__ dst, const Dom<R>* __restrict__ doms, const Tile* __restrict__ tiles,
     int ntiles, R* __restrict__ side, int from) {
-    __shared__ R lds[step3_wall_lds<TW, TH>()];
+    __shared__ R lds[step3_wall_lds<R, TW, TH, NT>()];
     const Tile tl = tiles[xcd_tile(blockIdx.x, ntiles)];
     step3_wall_tile<R, TW, TH, NT>(lds, tl, src, dst, doms, side, from);
 }
@@ -1187,11 +1203,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 // the general path's (the larger); the window path uses its start.
 template <typename R, int TW, int TH, int NT, bool Sourced>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
-    lds_waves_per_eu(step3_wall_lds<TW, TH>() * (int)sizeof(R), NT)))) void step3_mixed_kernel(
+    lds_waves_per_eu(step3_wall_lds<R, TW, TH, NT>() * (int)sizeof(R), NT)))) void step3_mixed_kernel(
     const R* __restrict__ src, R* __restrict__ dst, const Dom<R>* __restrict__ doms, const Tile* __restrict__ tiles,
     int ntiles, R* __restrict__ side, int from) {
-    static_assert(step3_wall_lds<TW, TH>() >= step3_window_lds<TW, TH>(), "the general path's LDS is the larger");
-    __shared__ R lds[step3_wall_lds<TW, TH>()];
+    static_assert(step3_wall_lds<R, TW, TH, NT>() >= step3_window_lds<TW, TH>(), "the general path's LDS is the larger");
+    __shared__ R lds[step3_wall_lds<R, TW, TH, NT>()];
     const Tile tl = tiles[xcd_tile(blockIdx.x, ntiles)];
     if (tl.flags & 2) step3_window_tile<R, TW, TH, NT, Sourced>(lds, tl, src, dst, doms);
     else step3_wall_tile<R, TW, TH, NT>(lds, tl, src, dst, doms, side, from);
