@@ -1048,8 +1048,8 @@ def test_channel_profiles_match_startup_series():
 def test_benchmark_channels_50000_steps():
     """The 128 channels of the benchmark (W 32-256 with temperature walls, L
     256-2048 periodic, half Couette, half Poiseuille; started from rest) in the
-    benchmark's three-step launch (32x16, both kinds of tile in one launch, the
-    autotuner's choice for this batch) for 5 x 10^4 steps.  A channel stays uniform
+    benchmark's three-step launch (32x32 tiles, every tile on the general
+    kernel: the autotuner's choice for this batch) for 5 x 10^4 steps.  A channel stays uniform
     along y, so each of its rows equals the oracle's run on a periodic strip of
     4 rows with the same width and parameters: every ninth channel is compared
     with that run at the FP32 bar (rho, u, T), every channel is checked to be
@@ -1064,8 +1064,8 @@ def test_benchmark_channels_50000_steps():
     for i, s in enumerate(specs):
         ders.append(b.set_params(i, sides=lbm13.make_sides(*s["sides"]), **s["kw"]))
         b.init_moments(i, *bench.spec_fields(s))
-    b.set_fused_tile(32, 16)
-    b.set_interior_kernel(2)
+    b.set_fused_tile(32, 32)
+    b.set_interior_kernel(0)
     b.set_steps_per_launch(3)
     b.use_graph(120)
     steps = 50000
